@@ -1,0 +1,355 @@
+"""Pins of the CPU oracle against the mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: KKT
+conditions, brute-force active sets, closed forms, a Monte-Carlo covariance,
+invariances of the problem, and hand-derived worked examples.  Sizes keep the
+whole file to well under a minute on a few CPU cores.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import pins
+from paper_1402_2518_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _run(oracle_lib, S, X, sigma=None, **kw):
+    return oracle_lib.unmix(S, X, sigma, **kw)
+
+
+def _sample(name, n):
+    w = synth.WORKLOADS[name]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w, p1=n)
+    return S, X, s
+
+
+# ---------------------------------------------------------------- KKT -----
+
+@pytest.mark.parametrize("name,n", [("tiny", 1000), ("orbital", 1500), ("precision", 200)])
+def test_kkt_on_workloads(oracle_lib, name, n):
+    """Natural residual, feasibility, dual feasibility, complementarity."""
+    S, X, s = _sample(name, n)
+    r = _run(oracle_lib, S, X, s, cov=False)
+    G = pins.gram(S)
+    B = pins.proj(S, X)
+    ok = (r["status"] & ~np.uint8(oracle_lib.DEGENERATE)) == 0
+    assert ok.all(), np.bincount(r["status"])
+    a, lam = r["a"], r["lam"]
+    assert pins.natural_residual(G, B, a).max() <= 1e-10
+    assert a.min() >= -1e-14
+    assert np.abs(a.sum(1) - 1).max() <= 1e-13
+    # multipliers recomputed from a (scaled units): lambda = Gh a - bh + nu
+    gam = G.diagonal().max()
+    lam_re = a @ (G / gam) - B / gam + r["nu"][:, None]
+    assert lam_re.min() >= -1e-10
+    assert np.abs(lam - lam_re).max() <= 1e-10
+    assert (a * np.maximum(lam_re, 0)).max() <= 1e-12
+    # iteration counts stay far from the cap
+    assert r["iters"].max() < 40
+
+
+# --------------------------------------------------------- brute force ----
+
+def test_brute_force_tiny_workload(oracle_lib):
+    """All 1,000 pixels of the N=8 workload vs enumeration of 255 active sets."""
+    S, X, s = _sample("tiny", 1000)
+    r = _run(oracle_lib, S, X, s, cov=False)
+    a_bf, lam_bf = pins.brute_force(pins.gram(S), pins.proj(S, X))
+    assert np.abs(r["a"] - a_bf).max() <= 1e-9
+    assert lam_bf.min() >= -1e-9 * np.abs(lam_bf).max()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8])
+def test_brute_force_random_libraries(oracle_lib, N):
+    rng = np.random.default_rng(100 + N)
+    L = int(rng.integers(max(N, 4), 40))
+    S = rng.uniform(0.05, 1.0, (N, L)).astype(np.float32)
+    X = (rng.dirichlet(np.ones(N), 200) @ S + 0.05 * rng.standard_normal((200, L))).astype(np.float32)
+    r = _run(oracle_lib, S, X, cov=False)
+    a_bf, _ = pins.brute_force(pins.gram(S), pins.proj(S, X))
+    assert np.abs(r["a"] - a_bf).max() <= 1e-9
+
+
+# --------------------------------------------------------- closed forms ---
+
+@pytest.mark.parametrize("N,L", [(5, 64), (36, 240), (96, 438)])
+def test_identity_gram_is_simplex_projection(oracle_lib, N, L):
+    """G = c I exactly (disjoint equal supports): a* = P_simplex(b / c)."""
+    rng = np.random.default_rng(N)
+    S = pins.disjoint_library(N, L, rng, equal=True)
+    X = (rng.uniform(0, 1, (64, L)) * 0.5).astype(np.float32)
+    r = _run(oracle_lib, S, X)
+    G = pins.gram(S)
+    c = G[0, 0]
+    assert np.allclose(G, c * np.eye(N), rtol=0, atol=0)
+    want = pins.simplex_project(pins.proj(S, X) / c)
+    assert np.abs(r["a"] - want).max() <= 1e-12
+    # covariance on the free set: (s^2/c)(I - 1 1^T / |F|)
+    for p in range(8):
+        F = want[p] > 0
+        k = F.sum()
+        exp = np.zeros((N, N))
+        exp[np.ix_(F, F)] = (np.eye(k) - 1.0 / k) / c
+        assert np.abs(r["cov"][p] - exp).max() <= 1e-12 * max(1.0, 1.0 / c)
+
+
+@pytest.mark.parametrize("N", [4, 17, 64])
+def test_diagonal_gram_is_water_filling(oracle_lib, N):
+    rng = np.random.default_rng(7 * N)
+    L = 4 * N
+    S = pins.disjoint_library(N, L, rng)
+    X = (rng.uniform(0, 1, (32, L)) * 0.6).astype(np.float32)
+    r = _run(oracle_lib, S, X, cov=False)
+    g = np.diag(pins.gram(S))
+    B = pins.proj(S, X)
+    for p in range(len(X)):
+        assert np.abs(r["a"][p] - pins.water_filling(g, B[p])).max() <= 1e-11
+
+
+def test_two_endmembers_closed_form(oracle_lib):
+    rng = np.random.default_rng(2)
+    S = rng.uniform(0.1, 0.6, (2, 50)).astype(np.float32)
+    X = np.concatenate([
+        rng.uniform(0.0, 0.7, (50, 50)),          # mostly clipped at 0 or 1
+        (rng.uniform(0.2, 0.8, (50, 1)) * S[0] + (1 - rng.uniform(0.2, 0.8, (50, 1))) * S[1]
+         + 0.01 * rng.standard_normal((50, 50))),
+    ]).astype(np.float32)
+    r = _run(oracle_lib, S, X, cov=False)
+    for p in range(len(X)):
+        want = pins.two_endmembers(S[0].astype(float), S[1].astype(float), X[p].astype(float))
+        assert np.abs(r["a"][p] - want).max() <= 1e-10
+
+
+def test_single_endmember(oracle_lib):
+    rng = np.random.default_rng(3)
+    S = rng.uniform(0.1, 0.6, (1, 30)).astype(np.float32)
+    X = rng.uniform(0, 1, (10, 30)).astype(np.float32)
+    r = _run(oracle_lib, S, X, np.full(10, 0.01, np.float32))
+    assert np.all(r["a"] == 1.0)
+    assert np.all(r["cov"] == 0.0)
+
+
+def test_interior_optimum_equals_scls(oracle_lib):
+    """Interior minimiser = sum-to-one-only closed form (SCLS, Sec. 2.2)."""
+    rng = np.random.default_rng(5)
+    N, L = 6, 80
+    S = synth.mineral_spectra(N, L, rng).astype(np.float32)
+    a_true = rng.dirichlet(np.ones(N) * 20, 40)
+    X = (a_true @ S.astype(float) + 1e-4 * rng.standard_normal((40, L))).astype(np.float32)
+    r = _run(oracle_lib, S, X, cov=False)
+    G, B = pins.gram(S), pins.proj(S, X)
+    n_int = 0
+    for p in range(len(X)):
+        want = pins.scls(G, B[p])
+        if want.min() > 1e-3:
+            n_int += 1
+            assert np.abs(r["a"][p] - want).max() <= 1e-9
+    assert n_int >= 30
+
+
+def test_exact_recovery_dyadic(oracle_lib):
+    """y = S^T a_true exactly in float32 (dyadic values): a* = a_true."""
+    rng = np.random.default_rng(11)
+    N, L = 8, 64
+    S = (rng.integers(1, 256, (N, L)) / 256.0).astype(np.float32)
+    fracs = [(0.5, 0.5), (0.5, 0.25, 0.25), (1.0,), (0.75, 0.125, 0.125)]
+    A = np.zeros((40, N))
+    for p in range(40):
+        f = fracs[p % len(fracs)]
+        idx = rng.choice(N, len(f), replace=False)
+        A[p, idx] = f
+    Xd = A @ S.astype(np.float64)
+    X = Xd.astype(np.float32)
+    assert np.array_equal(X.astype(np.float64), Xd)
+    r = _run(oracle_lib, S, X, np.full(40, 0.01, np.float32), cov=False)
+    assert np.abs(r["a"] - A).max() <= 1e-10
+
+
+def test_generator_noise_free_recovery(oracle_lib):
+    """Noise-free generator cube: a* within float32 rounding of y of a_true."""
+    w = synth.WORKLOADS["tiny"]
+    S = synth.make_library(w)
+    X, s, A = synth.make_cube(w, p1=300, noise=False, with_truth=True)
+    r = _run(oracle_lib, S, X, s, cov=False)
+    assert np.abs(r["a"] - A).max() <= 2e-5
+
+
+# ---------------------------------------------------------- covariance ----
+
+def test_covariance_vs_bordered_inverse(oracle_lib):
+    S, X, s = _sample("tiny", 300)
+    r = _run(oracle_lib, S, X, s)
+    G = pins.gram(S)
+    for p in range(300):
+        if r["status"][p]:
+            continue
+        free = r["a"][p] > r["lam"][p]
+        want = pins.bordered_cov(G, free, float(s[p]))
+        assert np.abs(r["cov"][p] - want).max() <= 1e-8 * np.abs(want).max() + 1e-18
+
+
+def test_covariance_invariants(oracle_lib):
+    S, X, s = _sample("orbital", 300)
+    r = _run(oracle_lib, S, X, s)
+    for p in range(300):
+        cv = r["cov"][p]
+        assert np.abs(cv - cv.T).max() <= 1e-12 * np.abs(cv).max()
+        ev = np.linalg.eigvalsh(cv)
+        assert ev.min() >= -1e-9 * ev.max()
+        assert np.abs(cv.sum(1)).max() <= 1e-8 * np.abs(cv).max()
+        act = r["a"][p] == 0
+        assert np.all(cv[act] == 0) and np.all(cv[:, act] == 0)
+    # proportional to s^2 (s is float32, so 3 s carries its own rounding)
+    s3 = (s[:20] * 3).astype(np.float32)
+    r2 = _run(oracle_lib, S, X[:20], s3)
+    ratio = (s3.astype(float) / s[:20].astype(float)) ** 2
+    assert np.allclose(r2["cov"], ratio[:, None, None] * r["cov"][:20], rtol=1e-12, atol=0)
+    assert np.array_equal(r2["a"], r["a"][:20])
+
+
+def test_covariance_monte_carlo(oracle_lib):
+    """Empirical covariance of the estimates over noise draws matches."""
+    rng = np.random.default_rng(17)
+    N, L, K = 4, 64, 4000
+    S = synth.mineral_spectra(N, L, rng).astype(np.float32)
+    a_true = np.full(N, 0.25)
+    s = 0.002
+    X = (a_true @ S.astype(float) + s * rng.standard_normal((K, L))).astype(np.float32)
+    r = _run(oracle_lib, S, X, np.full(K, s, np.float32))
+    assert (r["a"].min(1) > 0).all()  # stays interior
+    emp = np.cov(r["a"].T)
+    model = r["cov"].mean(0)
+    d = np.sqrt(np.diag(model))
+    assert np.abs(np.diag(emp) / np.diag(model) - 1).max() <= 0.1
+    assert np.abs((emp - model) / np.outer(d, d)).max() <= 0.1
+
+
+# ---------------------------------------------------------- invariances ---
+
+def test_permutation_invariance(oracle_lib):
+    S, X, s = _sample("orbital", 200)
+    perm = np.random.default_rng(1).permutation(S.shape[0])
+    r1 = _run(oracle_lib, S, X, s)
+    r2 = _run(oracle_lib, S[perm], X, s)
+    assert np.abs(r2["a"] - r1["a"][:, perm]).max() <= 1e-8
+    ok = (r1["status"] == 0) & (r2["status"] == 0)
+    c1 = r1["cov"][ok][:, perm][:, :, perm]
+    assert np.abs(r2["cov"][ok] - c1).max() <= 1e-6 * np.abs(c1).max()
+
+
+def test_noise_covariance_renormalisation(oracle_lib):
+    """Eqs. 5-6: whitening with any factor of C^-1 gives the same minimiser;
+    scaling C scales the covariance and leaves a unchanged."""
+    rng = np.random.default_rng(23)
+    N, L = 6, 40
+    S = synth.mineral_spectra(N, L, rng).astype(np.float32)
+    Q = rng.standard_normal((L, L))
+    C = Q @ Q.T / L + np.diag(rng.uniform(0.5, 2.0, L))
+    X = (rng.dirichlet(np.ones(N), 100) @ S.astype(float)
+         + 0.01 * rng.standard_normal((100, L))).astype(np.float32)
+    r = _run(oracle_lib, S, X, np.full(100, 1.0, np.float32), C=C)
+    # reference: symmetric inverse square root of C (not a Cholesky factor)
+    ev, V = np.linalg.eigh(C)
+    Wh = V @ np.diag(ev ** -0.5) @ V.T
+    Sw, Xw = S.astype(float) @ Wh, X.astype(float) @ Wh
+    a_bf, _ = pins.brute_force(Sw @ Sw.T, Xw @ Sw.T)
+    assert np.abs(r["a"] - a_bf).max() <= 1e-9
+    # F = (x - aS) C^-1 (x - aS)^T / s^2
+    res = X.astype(float) - r["a"] @ S.astype(float)
+    F = np.einsum("pl,pl->p", res, np.linalg.solve(C, res.T).T)
+    assert np.abs(r["F"] / F - 1).max() <= 1e-9
+    r100 = _run(oracle_lib, S, X, np.full(100, 1.0, np.float32), C=100 * C)
+    assert np.abs(r100["a"] - r["a"]).max() <= 1e-9
+    assert np.allclose(r100["cov"], 100 * r["cov"], rtol=1e-6, atol=1e-14)
+    assert np.allclose(r100["F"], r["F"] / 100, rtol=1e-9)
+    with pytest.raises(ValueError):
+        oracle_lib.renormalise(S, -np.eye(L))
+
+
+def test_objective_residual_form(oracle_lib):
+    S, X, s = _sample("orbital", 200)
+    r = _run(oracle_lib, S, X, s, cov=False)
+    res = X.astype(float) - r["a"] @ S.astype(float)
+    F = (res ** 2).sum(1) / s.astype(float) ** 2
+    assert np.abs(r["F"] / F - 1).max() <= 1e-8
+    # noise-consistent fit: F ~ L - (free coefficients)
+    assert 0.7 * S.shape[1] < np.median(F) < 1.1 * S.shape[1]
+
+
+def test_adding_a_spectrum_never_increases_objective(oracle_lib):
+    w = synth.WORKLOADS["tiny"]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w, p1=200)
+    r_small = _run(oracle_lib, S[:7], X, s, cov=False)
+    r_full = _run(oracle_lib, S, X, s, cov=False)
+    assert (r_full["F"] <= r_small["F"] * (1 + 1e-12)).all()
+
+
+def test_duplicate_spectrum_splits_weight(oracle_lib):
+    S, X, s = _sample("tiny", 100)
+    Sd = np.concatenate([S, S[:1]])
+    r = _run(oracle_lib, S, X, s, cov=False)
+    rd = _run(oracle_lib, Sd, X, s, cov=False)
+    # the split of a duplicated spectrum is not unique, so the finishing step
+    # cannot certify those pixels (INEXACT) and they stay at the interior-point
+    # accuracy; pixels where the spectrum is inactive stay exact
+    assert np.abs(rd["a"][:, 0] + rd["a"][:, -1] - r["a"][:, 0]).max() <= 1e-5
+    assert np.abs(rd["a"][:, 1:-1] - r["a"][:, 1:]).max() <= 1e-5
+    assert np.abs(rd["F"] / r["F"] - 1).max() <= 1e-7
+    exact = rd["status"] == 0
+    assert exact.sum() >= 20 and (r["a"][exact, 0] == 0).all()
+    assert np.abs(rd["a"][exact, :-1] - r["a"][exact]).max() <= 1e-9
+    inexact = (rd["status"] & oracle_lib.INEXACT) != 0
+    assert inexact.sum() >= 20 and (r["a"][inexact, 0] > 0).all()
+
+
+# ------------------------------------------------------------- status -----
+
+def test_status_flags_and_isolation(oracle_lib):
+    S, X, s = _sample("tiny", 20)
+    X = X.copy()
+    s = s.copy()
+    X[3, 5] = np.nan
+    X[4, 0] = np.inf
+    s[7] = 0.0
+    s[8] = -1.0
+    r = _run(oracle_lib, S, X, s)
+    ref = _run(oracle_lib, S, np.delete(X, [3, 4], 0), np.delete(s, [3, 4], 0))
+    assert r["status"][3] & oracle_lib.NONFINITE and r["status"][4] & oracle_lib.NONFINITE
+    assert np.isnan(r["a"][3]).all() and np.isnan(r["cov"][4]).all()
+    assert r["status"][7] & oracle_lib.BAD_SIGMA and r["status"][8] & oracle_lib.BAD_SIGMA
+    assert np.isnan(r["F"][7]) and np.isnan(r["cov"][8]).all()
+    assert np.isfinite(r["a"][7]).all()
+    keep = [i for i in range(20) if i not in (3, 4)]
+    assert np.array_equal(r["a"][keep], ref["a"])
+    rm = _run(oracle_lib, S, X[:3], s[:3], maxit=1)
+    assert (rm["status"] & oracle_lib.MAXIT).all()
+
+
+def test_empty_input(oracle_lib):
+    S, X, s = _sample("tiny", 1)
+    r = _run(oracle_lib, S, X[:0], s[:0])
+    assert r["a"].shape == (0, S.shape[0])
+
+
+# ------------------------------------------------------- worked examples --
+
+def test_worked_examples_golden(oracle_lib):
+    """Hand-derived examples (derivations in the fixture file)."""
+    with open(os.path.join(GOLDEN, "worked_examples.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        S = np.array(c["S"], np.float32)
+        X = np.array(c["X"], np.float32)
+        sig = np.array(c["sigma"], np.float32)
+        r = _run(oracle_lib, S, X, sig)
+        assert np.abs(r["a"] - np.array(c["a"])).max() <= 1e-12, c["name"]
+        if "cov" in c:
+            assert np.abs(r["cov"] - np.array(c["cov"])).max() <= 1e-12, c["name"]
+        if "F" in c:
+            assert np.abs(r["F"] - np.array(c["F"])).max() <= 1e-9 * np.abs(c["F"]).max(), c["name"]

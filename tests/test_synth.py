@@ -1,0 +1,50 @@
+"""Generator checks: shapes, value ranges, support sizes, determinism."""
+import numpy as np
+
+from paper_1402_2518_amd import synth
+
+
+def test_library_shapes_and_ranges():
+    for name, w in synth.WORKLOADS.items():
+        S = synth.make_library(w)
+        assert S.shape == (w.N, w.L) and S.dtype == np.float32
+        m = S[: w.n_minerals]
+        assert m.min() > 0.0 and m.max() <= 0.6 + 1e-6
+        assert np.array_equal(S, synth.make_library(w))
+        if w.n_extra:
+            assert np.all(S[w.n_minerals] == 1.0)
+
+
+def test_cube_ranges_support_and_slices():
+    w = synth.WORKLOADS["orbital"]
+    S = synth.make_library(w)
+    X, s, A = synth.make_cube(w, S, p1=3 * synth.CHUNK + 17, with_truth=True)
+    assert X.dtype == np.float32 and s.dtype == np.float32
+    assert (s >= 0.002).all() and (s <= 0.01).all()
+    assert np.allclose(A.sum(1), 1.0)
+    k = (A[:, : w.n_minerals] > 0).sum(1)
+    assert k.min() == 1 and k.max() == 4
+    assert (A[:, w.n_minerals:] > 0).all()
+    # any pixel range reproduces the same bytes as the corresponding slice
+    X2, s2 = synth.make_cube(w, S, p0=synth.CHUNK - 5, p1=2 * synth.CHUNK + 9)
+    assert np.array_equal(X2, X[synth.CHUNK - 5: 2 * synth.CHUNK + 9])
+    assert np.array_equal(s2, s[synth.CHUNK - 5: 2 * synth.CHUNK + 9])
+    # noise level consistent with sigma
+    resid = X.astype(float) - A @ S.astype(float)
+    assert 0.9 < np.median(np.std(resid, axis=1) / s) < 1.1
+
+
+def test_tiny_workload():
+    w = synth.WORKLOADS["tiny"]
+    X, s, A = synth.make_cube(w, with_truth=True)
+    assert X.shape == (1000, 64) and (s == np.float32(0.005)).all()
+    k = (A > 0).sum(1)
+    assert k.min() == 1 and k.max() == 3
+
+
+def test_paper_extra_spectra():
+    E4 = synth.paper_extra_spectra(110, 4)
+    assert E4.shape == (4, 110)
+    assert np.linalg.matrix_rank(E4) == 2
+    E12 = synth.paper_extra_spectra(110, 12)
+    assert E12.shape == (12, 110) and E12.min() >= 0
