@@ -1,0 +1,156 @@
+/*
+ * linmin.h -- C ABI of lib_linmin, per-pixel constrained linear unmixing of
+ * hyperspectral cubes on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Schmidt, Legendre & Le Mouelic, "Minerals detection for
+ * hyperspectral images using adapted linear unmixing: LinMin"):
+ *   - linear mixing model X = A S + E (Sec. 2.1, eq. 1);
+ *   - per pixel, the least-squares criterion (eq. 2), renormalised by the
+ *     noise covariance C^{-1} = L L^T (Sec. 2.3, eqs. 5-6);
+ *   - positivity a >= 0 (eq. 3) and sum-to-one 1^T a = 1 (eq. 4), solved by
+ *     a primal-dual interior-point method (IPLS, Sec. 2.2) with an exact
+ *     finishing step on the identified free set;
+ *   - the coefficient covariance "provided by the Hessian" (end of Sec. 2.3).
+ *
+ * Conventions shared by every entry point:
+ *   - Library S: N x L float32, row-major, one reference spectrum per row
+ *     (the paper's S).  Cube X: P x L float32, row-major, one pixel spectrum
+ *     per row (band-interleaved-by-pixel).  sigma: P float32 per-pixel noise
+ *     scales s_p; the pixel's noise covariance is s_p^2 C.
+ *   - Outputs are FP64.  Coefficients: P x N row-major.
+ *   - Pointers documented as "device" must be device memory (hipMalloc, or a
+ *     torch CUDA tensor's data_ptr) on the current HIP device; "host" means
+ *     ordinary host memory.  The caller owns every buffer it passes.
+ *   - Return codes are LINMIN_OK or a negative LINMIN_E* value; they report
+ *     misuse or HIP failures, never per-pixel numerical trouble (that goes
+ *     to the optional per-pixel status array).
+ */
+#ifndef LINMIN_H
+#define LINMIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct linmin_lib_s *linmin_lib;
+
+/* return codes */
+#define LINMIN_OK 0
+#define LINMIN_EINVAL (-1)       /* bad argument (NULL, size out of range, N > L, ...) */
+#define LINMIN_ENOMEM (-2)       /* device or host allocation failed */
+#define LINMIN_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define LINMIN_ENOTSPD (-4)      /* noise covariance not symmetric positive definite,
+                                    or the library's Gram matrix is not positive */
+#define LINMIN_EUNSUPPORTED (-5) /* option combination not built in */
+
+/* precision of the interior-point iterations */
+#define LINMIN_FP64 0  /* every step in FP64 */
+#define LINMIN_MIXED 1 /* FP32 Newton steps until mu <= mu_switch, then FP64 */
+
+/* covariance output layouts (per pixel) */
+#define LINMIN_COV_NONE 0   /* out_cov ignored */
+#define LINMIN_COV_FULL 1   /* N x N row-major */
+#define LINMIN_COV_PACKED 2 /* lower triangle row by row, N (N+1) / 2 values */
+#define LINMIN_COV_DIAG 3   /* N variances */
+
+/* per-pixel status bits (0 = solved and certified) */
+#define LINMIN_PX_MAXIT 1u       /* interior-point iteration cap reached */
+#define LINMIN_PX_NONFINITE 2u   /* spectrum has NaN/Inf; outputs are NaN */
+#define LINMIN_PX_BAD_SIGMA 4u   /* s_p <= 0 or not finite; covariance and
+                                    objective are NaN, coefficients valid */
+#define LINMIN_PX_NOT_PD 8u      /* a Newton matrix lost positive definiteness */
+#define LINMIN_PX_DEGENERATE 16u /* certified, but some index has both a_i and
+                                    its multiplier below deg_tol (no strict
+                                    complementarity): covariance is one of
+                                    several valid choices */
+#define LINMIN_PX_INEXACT 32u    /* the finishing step could not certify the
+                                    free set; outputs are the last interior
+                                    iterate */
+
+#define LINMIN_N_MAX 128 /* largest library supported */
+
+typedef struct {
+    int precision;      /* LINMIN_FP64 or LINMIN_MIXED */
+    int cov_layout;     /* LINMIN_COV_* */
+    int maxit;          /* interior-point iteration cap (default 100) */
+    int max_polish;     /* partition corrections in the finishing step (16) */
+    double tol_mu;      /* stop when mu <= tol_mu (1e-13) ...          */
+    double tol_d;       /* ... ||r_d||_inf <= tol_d (1 + ||bh||_inf) (1e-12) */
+    double tol_p;       /* ... and |1^T a - 1| <= tol_p (1e-13)        */
+    double eta;         /* fraction of the step to the boundary (0.99) */
+    double lambda0;     /* starting multipliers (0.1) */
+    double tau;         /* KKT sign tolerance of the finishing step (1e-11) */
+    double deg_tol;     /* strict-complementarity threshold (1e-9) */
+    double mu_switch;   /* MIXED: FP32 -> FP64 hand-over point (1e-7) */
+    uint8_t *status;    /* device, P entries or NULL: LINMIN_PX_* bits */
+    int32_t *iters;     /* device, P entries or NULL: interior-point iterations */
+    double *objective;  /* device, P entries or NULL: renormalised criterion
+                           F_p = (x' - a S')(x' - a S')^T / s_p^2 (eq. 6) */
+    void **stage_events; /* NULL, or 4 caller-created hipEvent_t recorded on the
+                            stream before the projections, before the
+                            interior-point solve, before the covariance pass
+                            and after it (stage timing without a profiler) */
+} linmin_opts;
+
+/* Fill *opts with the defaults quoted above (pointer members NULL). */
+void linmin_default_opts(linmin_opts *opts);
+
+/*
+ * Build a reference library (Sec. 2.1 S, renormalised per Sec. 2.3).
+ *   S          host, N x L float32 row-major (copied).
+ *   L, N       1 <= N <= min(L, LINMIN_N_MAX) (the paper limits the number of
+ *              spectra to the number of wavelengths, Sec. 2.4).
+ *   noise_cov  host, L x L FP64 row-major symmetric positive definite, or
+ *              NULL for C = I (copied).
+ *   out        receives the handle.
+ * Runs synchronously on the current device: it computes W = C^{-1} S^T,
+ * the Gram matrix G = S C^{-1} S^T (on MFMA), gamma = max_i G_ii and the
+ * scaled copies used by unmix.  The handle is immutable afterwards and may be
+ * used from several streams at once.  Errors: EINVAL, ENOMEM, EHIP, ENOTSPD.
+ */
+int linmin_create_library(const float *S, int L, int N, const double *noise_cov, linmin_lib *out);
+
+/*
+ * Unmix P pixels (Sec. 2.2 under eqs. 3-4, renormalised per eq. 6).
+ *   cube        device, P x L float32 row-major.
+ *   P           >= 0; P == 0 is a no-op.
+ *   sigma       device, P float32 s_p, or NULL for s_p = 1.  Coefficients do
+ *               not depend on s_p; covariance scales with s_p^2 and the
+ *               objective with 1 / s_p^2.
+ *   out_coeffs  device, P x N FP64: the mixing coefficients.
+ *   out_cov     device, per-pixel covariance in opts->cov_layout (P x N x N,
+ *               P x N(N+1)/2 or P x N FP64), or NULL (then no covariance is
+ *               computed whatever the layout).
+ *   opts        NULL for defaults (FP64, COV_FULL).
+ *   stream      hipStream_t to enqueue on, NULL for the default stream.
+ * Asynchronous like a kernel launch: returns once the work is enqueued.
+ * Temporary device memory (about P (N + 2) doubles) is taken from the
+ * stream-ordered allocator and released on the same stream.  Errors:
+ * EINVAL (NULL handle/buffers, P < 0), EUNSUPPORTED, ENOMEM, EHIP.
+ */
+int linmin_unmix(linmin_lib lib, const float *cube, int64_t P, const float *sigma,
+                 double *out_coeffs, double *out_cov, const linmin_opts *opts, void *stream);
+
+/* Bytes of temporary device memory linmin_unmix takes for these arguments. */
+size_t linmin_workspace_bytes(linmin_lib lib, int64_t P, const linmin_opts *opts);
+
+/* Library shape and scale: any output pointer may be NULL.  gamma is
+ * max_i G_ii of the renormalised Gram matrix.  Returns EINVAL for NULL lib. */
+int linmin_library_info(linmin_lib lib, int *L, int *N, double *gamma);
+
+/* Copy the renormalised Gram matrix G (N x N FP64) to host memory. */
+int linmin_library_gram(linmin_lib lib, double *G_host);
+
+/* Release a library (after all work using it has completed). */
+int linmin_destroy_library(linmin_lib lib);
+
+/* Static text for a return code. */
+const char *linmin_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LINMIN_H */

@@ -1,0 +1,138 @@
+// common.h -- device helpers shared by the lib_linmin HIP kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace lm {
+
+// ---------------------------------------------------------------------------
+// Lane moves inside a group.  Groups of G consecutive lanes (G = 1, 2, 4, 8,
+// 16, 32) work on one pixel; every cross-lane operation below stays inside
+// the group (DPP within a 16-lane row, one xor-16 shuffle for 32-lane
+// groups), so it never mixes pixels.
+// ---------------------------------------------------------------------------
+constexpr int qp(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+constexpr int kRowMirror = 0x140;      // lane i <- lane 15-i within a row
+constexpr int kRowHalfMirror = 0x141;  // lane i <- lane 7-i within each half-row
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = dpp_i32<CTRL>(lo);
+  hi = dpp_i32<CTRL>(hi);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return dpp_i32<CTRL>(v);
+}
+
+// Sum / max / min over the group; every lane of the group gets the same bits
+// (each butterfly step adds the same two operands on both partner lanes).
+// lane i <- lane i^16 (crosses DPP rows; only used by 32-lane groups)
+template <typename T>
+__device__ __forceinline__ T xor16(T v) {
+  return __shfl_xor(v, 16);
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T gsum(T v) {
+  static_assert(G <= 32, "group wider than half a wave");
+  if constexpr (G >= 2) v += dpp<qp(1, 0, 3, 2)>(v);
+  if constexpr (G >= 4) v += dpp<qp(2, 3, 0, 1)>(v);
+  if constexpr (G >= 8) v += dpp<kRowHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp<kRowMirror>(v);
+  if constexpr (G >= 32) v += xor16(v);
+  return v;
+}
+template <int G, typename T>
+__device__ __forceinline__ T gmax(T v) {
+  if constexpr (G >= 2) v = fmax(v, dpp<qp(1, 0, 3, 2)>(v));
+  if constexpr (G >= 4) v = fmax(v, dpp<qp(2, 3, 0, 1)>(v));
+  if constexpr (G >= 8) v = fmax(v, dpp<kRowHalfMirror>(v));
+  if constexpr (G >= 16) v = fmax(v, dpp<kRowMirror>(v));
+  if constexpr (G >= 32) v = fmax(v, xor16(v));
+  return v;
+}
+template <int G, typename T>
+__device__ __forceinline__ T gmin(T v) {
+  if constexpr (G >= 2) v = fmin(v, dpp<qp(1, 0, 3, 2)>(v));
+  if constexpr (G >= 4) v = fmin(v, dpp<qp(2, 3, 0, 1)>(v));
+  if constexpr (G >= 8) v = fmin(v, dpp<kRowHalfMirror>(v));
+  if constexpr (G >= 16) v = fmin(v, dpp<kRowMirror>(v));
+  if constexpr (G >= 32) v = fmin(v, xor16(v));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int gmin_i(int v) {
+  if constexpr (G >= 2) v = min(v, dpp<qp(1, 0, 3, 2)>(v));
+  if constexpr (G >= 4) v = min(v, dpp<qp(2, 3, 0, 1)>(v));
+  if constexpr (G >= 8) v = min(v, dpp<kRowHalfMirror>(v));
+  if constexpr (G >= 16) v = min(v, dpp<kRowMirror>(v));
+  if constexpr (G >= 32) v = min(v, xor16(v));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int gor_i(int v) {
+  if constexpr (G >= 2) v |= dpp<qp(1, 0, 3, 2)>(v);
+  if constexpr (G >= 4) v |= dpp<qp(2, 3, 0, 1)>(v);
+  if constexpr (G >= 8) v |= dpp<kRowHalfMirror>(v);
+  if constexpr (G >= 16) v |= dpp<kRowMirror>(v);
+  if constexpr (G >= 32) v |= xor16(v);
+  return v;
+}
+
+// Value held by group lane SRC (compile time), delivered to every lane of the
+// group.  t is the caller's lane index within the group.
+template <int G, int SRC, typename T>
+__device__ __forceinline__ T gbcast(T v, int t) {
+  static_assert(SRC >= 0 && SRC < G, "source lane outside group");
+  if constexpr (G == 1) {
+    return v;
+  } else if constexpr (G == 2) {
+    return dpp<qp(SRC, SRC, 2 + SRC, 2 + SRC)>(v);
+  } else {
+    v = dpp<qp(SRC & 3, SRC & 3, SRC & 3, SRC & 3)>(v);
+    if constexpr (G >= 8) {
+      T m = dpp<kRowHalfMirror>(v);
+      v = (((t >> 2) & 1) == ((SRC >> 2) & 1)) ? v : m;
+    }
+    if constexpr (G >= 16) {
+      T m = dpp<kRowMirror>(v);
+      v = (((t >> 3) & 1) == ((SRC >> 3) & 1)) ? v : m;
+    }
+    if constexpr (G >= 32) {
+      T m = xor16(v);
+      v = (((t >> 4) & 1) == ((SRC >> 4) & 1)) ? v : m;
+    }
+    return v;
+  }
+}
+
+// Fused multiply-add in the operand precision (no promotion of float).
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Orders this wave's LDS writes before its later LDS reads.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+}  // namespace lm

@@ -1,0 +1,74 @@
+// kernels.h -- launch interface between the C ABI (linmin.cpp) and the HIP
+// kernels of lib_linmin.  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lm {
+
+// Mode of an interior-point launch.
+enum IpmMode : int {
+  kFull = 0,    // start -> iterate to tolerance -> finishing step -> outputs
+  kStage1 = 1,  // start -> iterate until mu <= mu_switch -> save state
+  kStage2 = 2,  // load state -> iterate to tolerance -> finishing step -> outputs
+};
+
+// Per-pixel status bits (same meaning as LINMIN_PX_* in linmin.h).
+enum : uint32_t {
+  kPxMaxit = 1u,
+  kPxNonfinite = 2u,
+  kPxBadSigma = 4u,
+  kPxNotPd = 8u,
+  kPxDegenerate = 16u,
+  kPxInexact = 32u,
+};
+
+struct IpmParams {
+  int n;                // library size N
+  int64_t P;            // pixels in this launch
+  const void* Gh;       // NC x NC scaled Gram, padded (identity on padded diagonal), FP64 or FP32
+  const double* bh;     // P x n scaled projections bh = b / gamma
+  const double* c;      // P: x'^T x' (NULL when no objective is wanted)
+  const float* sigma;   // P or NULL (s_p = 1)
+  double gamma;         // max_i G_ii
+  int maxit;
+  int max_polish;
+  double tol_mu, tol_d, tol_p, eta, lambda0, tau, deg_tol, mu_switch;
+  // hand-over state between the FP32 and FP64 stages
+  double* st_a;         // P x n
+  double* st_lam;       // P x n
+  double* st_nu;        // P
+  int32_t* st_it;       // P
+  uint8_t* st_flag;     // P (status bits so far; bit 7: still iterating)
+  // outputs
+  double* out_a;        // P x n
+  uint8_t* status;      // P or NULL
+  int32_t* iters;       // P or NULL
+  double* objective;    // P or NULL
+  double* dcov;         // P x n or NULL: per-coefficient diagonal for the covariance pass
+};
+
+// ipm.hip: picks the compiled (NC, G) shape for n and precision.
+int ipm_shape_nc(int n);                  // padded size NC used for a library of size n
+int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st);
+
+// gemm.hip
+int launch_gemm_proj_f64(const float* Y, int64_t P, int L, const double* W, int ldw, int N,
+                         double* B, double* c, hipStream_t st);
+int launch_quadform_f64(const float* Y, int64_t P, int L, const double* Ci, int ldc, double* c,
+                        hipStream_t st);
+
+// cov.hip
+int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const float* sigma,
+               double gamma, const uint8_t* status_or_null, const double* out_a, int layout,
+               double* out_cov, hipStream_t st);
+
+// setup.hip
+int launch_setup(const float* S_dev, int L, int N, const double* C_dev /* L x L or NULL */,
+                 double* Ci_dev /* L x L out, when C given */, double* W_dev /* L x N out */,
+                 int* err_dev, hipStream_t st);
+int launch_gram_finish(const double* G_dev, int N, const double* W_dev, int L, int NC,
+                       double* Gh64, float* Gh32, double* Wh, int ldw, double* gamma_dev,
+                       int* err_dev, hipStream_t st);
+
+}  // namespace lm

@@ -1,0 +1,318 @@
+// linmin.cpp -- C ABI of lib_linmin (declared in include/linmin.h).
+//
+// Host side only: argument checks, device memory, and the order of kernel
+// launches.  All arithmetic of the path runs in the HIP kernels:
+//   create:  setup.hip (C^{-1}, W), gemm.hip (Gram on MFMA), setup.hip (scale)
+//   unmix:   gemm.hip (projections) -> ipm.hip (IPLS + finishing step)
+//            -> cov.hip (covariance)
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/linmin.h"
+#include "kernels.h"
+
+struct linmin_lib_s {
+  int L, N, NC, ldw, dev;
+  double gamma;
+  double* Wh;    // L x ldw, W / gamma
+  double* Gh64;  // NC x NC, G / gamma padded with identity
+  float* Gh32;   // NC x NC
+  double* G;     // N x N, unscaled Gram
+  double* Ci;    // L x L inverse noise covariance, or NULL for C = I
+};
+
+namespace {
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? LINMIN_OK : LINMIN_EHIP; }
+
+#define TRY(x)                   \
+  do {                           \
+    int rc_ = (x);               \
+    if (rc_ != LINMIN_OK) {      \
+      rc = rc_;                  \
+      goto fail;                 \
+    }                            \
+  } while (0)
+
+int from_launch(int r) {
+  if (r == 0) return LINMIN_OK;
+  if (r == -5) return LINMIN_EUNSUPPORTED;
+  if (r == -1) return LINMIN_EINVAL;
+  return LINMIN_EHIP;
+}
+
+void free_lib(linmin_lib l) {
+  if (!l) return;
+  (void)hipFree(l->Wh);
+  (void)hipFree(l->Gh64);
+  (void)hipFree(l->Gh32);
+  (void)hipFree(l->G);
+  (void)hipFree(l->Ci);
+  delete l;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Work {
+  size_t bh, c, dcov, st_a, st_lam, st_nu, st_it, st_flag, status, total;
+};
+
+Work plan(const linmin_lib_s* lib, int64_t P, const linmin_opts& o, bool want_cov) {
+  Work w{};
+  const size_t n = (size_t)lib->N, p = (size_t)P;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  w.bh = take(sizeof(double) * p * n);
+  w.c = take(sizeof(double) * p);
+  w.dcov = want_cov ? take(sizeof(double) * p * n) : (size_t)-1;
+  if (o.precision == LINMIN_MIXED) {
+    w.st_a = take(sizeof(double) * p * n);
+    w.st_lam = take(sizeof(double) * p * n);
+    w.st_nu = take(sizeof(double) * p);
+    w.st_it = take(sizeof(int32_t) * p);
+    w.st_flag = take(p);
+  } else {
+    w.st_a = w.st_lam = w.st_nu = w.st_it = w.st_flag = (size_t)-1;
+  }
+  w.status = (o.status == nullptr) ? take(p) : (size_t)-1;
+  w.total = off;
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+void linmin_default_opts(linmin_opts* o) {
+  if (!o) return;
+  o->precision = LINMIN_FP64;
+  o->cov_layout = LINMIN_COV_FULL;
+  o->maxit = 100;
+  o->max_polish = 16;
+  o->tol_mu = 1e-13;
+  o->tol_d = 1e-12;
+  o->tol_p = 1e-13;
+  o->eta = 0.99;
+  o->lambda0 = 0.1;
+  o->tau = 1e-11;
+  o->deg_tol = 1e-9;
+  o->mu_switch = 1e-7;
+  o->status = nullptr;
+  o->iters = nullptr;
+  o->objective = nullptr;
+  o->stage_events = nullptr;
+}
+
+const char* linmin_strerror(int code) {
+  switch (code) {
+    case LINMIN_OK: return "success";
+    case LINMIN_EINVAL: return "invalid argument";
+    case LINMIN_ENOMEM: return "out of memory";
+    case LINMIN_EHIP: return "HIP runtime or kernel launch failure";
+    case LINMIN_ENOTSPD: return "matrix not symmetric positive definite";
+    case LINMIN_EUNSUPPORTED: return "unsupported option combination";
+    default: return "unknown error";
+  }
+}
+
+int linmin_create_library(const float* S, int L, int N, const double* noise_cov, linmin_lib* out) {
+  if (!out) return LINMIN_EINVAL;
+  *out = nullptr;
+  if (!S || L < 1 || N < 1 || N > L || N > LINMIN_N_MAX) return LINMIN_EINVAL;
+  const int NC = lm::ipm_shape_nc(N);
+  if (NC < 0) return LINMIN_EUNSUPPORTED;
+  if (noise_cov)
+    for (int64_t i = 0; i < (int64_t)L * L; ++i)
+      if (!isfinite(noise_cov[i])) return LINMIN_ENOTSPD;
+
+  int rc = LINMIN_OK;
+  linmin_lib lib = new (std::nothrow) linmin_lib_s();
+  if (!lib) return LINMIN_ENOMEM;
+  lib->L = L;
+  lib->N = N;
+  lib->NC = NC;
+  lib->ldw = 16 * ((N + 15) / 16);
+  float* dS = nullptr;
+  double *dC = nullptr, *dW = nullptr, *dgam = nullptr;
+  int* derr = nullptr;
+  int herr = 0;
+  hipStream_t st = nullptr;
+  TRY(hip_ok(hipGetDevice(&lib->dev)));
+  TRY(hip_ok(hipStreamCreate(&st)));
+  {
+    const size_t wbytes = sizeof(double) * (size_t)L * lib->ldw;
+    if (hipMalloc(&dS, sizeof(float) * (size_t)N * L) != hipSuccess ||
+        hipMalloc(&dW, wbytes) != hipSuccess || hipMalloc(&lib->Wh, wbytes) != hipSuccess ||
+        hipMalloc(&lib->G, sizeof(double) * (size_t)N * N) != hipSuccess ||
+        hipMalloc(&lib->Gh64, sizeof(double) * (size_t)NC * NC) != hipSuccess ||
+        hipMalloc(&lib->Gh32, sizeof(float) * (size_t)NC * NC) != hipSuccess ||
+        hipMalloc(&dgam, sizeof(double)) != hipSuccess || hipMalloc(&derr, sizeof(int)) != hipSuccess) {
+      rc = LINMIN_ENOMEM;
+      goto fail;
+    }
+    if (noise_cov) {
+      if (hipMalloc(&dC, sizeof(double) * (size_t)L * L) != hipSuccess ||
+          hipMalloc(&lib->Ci, sizeof(double) * (size_t)L * L) != hipSuccess) {
+        rc = LINMIN_ENOMEM;
+        goto fail;
+      }
+      TRY(hip_ok(hipMemcpyAsync(dC, noise_cov, sizeof(double) * (size_t)L * L, hipMemcpyHostToDevice, st)));
+    }
+    TRY(hip_ok(hipMemcpyAsync(dS, S, sizeof(float) * (size_t)N * L, hipMemcpyHostToDevice, st)));
+    TRY(hip_ok(hipMemsetAsync(derr, 0, sizeof(int), st)));
+    TRY(from_launch(lm::launch_setup(dS, L, N, dC, lib->Ci, dW, derr, st)));
+    // Gram matrix G = S W on MFMA (library rows as pixels)
+    TRY(from_launch(lm::launch_gemm_proj_f64(dS, N, L, dW, lib->ldw, N, lib->G, nullptr, st)));
+    TRY(from_launch(lm::launch_gram_finish(lib->G, N, dW, L, NC, lib->Gh64, lib->Gh32, lib->Wh, lib->ldw,
+                                           dgam, derr, st)));
+    TRY(hip_ok(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st)));
+    TRY(hip_ok(hipMemcpyAsync(&lib->gamma, dgam, sizeof(double), hipMemcpyDeviceToHost, st)));
+    TRY(hip_ok(hipStreamSynchronize(st)));
+    if (herr != 0) {
+      rc = LINMIN_ENOTSPD;
+      goto fail;
+    }
+  }
+  (void)hipFree(dS);
+  (void)hipFree(dC);
+  (void)hipFree(dW);
+  (void)hipFree(dgam);
+  (void)hipFree(derr);
+  (void)hipStreamDestroy(st);
+  *out = lib;
+  return LINMIN_OK;
+fail:
+  if (st) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  (void)hipFree(dS);
+  (void)hipFree(dC);
+  (void)hipFree(dW);
+  (void)hipFree(dgam);
+  (void)hipFree(derr);
+  free_lib(lib);
+  return rc;
+}
+
+int linmin_destroy_library(linmin_lib lib) {
+  if (!lib) return LINMIN_EINVAL;
+  free_lib(lib);
+  return LINMIN_OK;
+}
+
+int linmin_library_info(linmin_lib lib, int* L, int* N, double* gamma) {
+  if (!lib) return LINMIN_EINVAL;
+  if (L) *L = lib->L;
+  if (N) *N = lib->N;
+  if (gamma) *gamma = lib->gamma;
+  return LINMIN_OK;
+}
+
+int linmin_library_gram(linmin_lib lib, double* G_host) {
+  if (!lib || !G_host) return LINMIN_EINVAL;
+  return hip_ok(hipMemcpy(G_host, lib->G, sizeof(double) * (size_t)lib->N * lib->N, hipMemcpyDeviceToHost));
+}
+
+size_t linmin_workspace_bytes(linmin_lib lib, int64_t P, const linmin_opts* opts) {
+  if (!lib || P <= 0) return 0;
+  linmin_opts o;
+  if (opts) o = *opts;
+  else linmin_default_opts(&o);
+  return plan(lib, P, o, o.cov_layout != LINMIN_COV_NONE).total;
+}
+
+int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigma, double* out_coeffs,
+                 double* out_cov, const linmin_opts* opts, void* stream) {
+  if (!lib || P < 0) return LINMIN_EINVAL;
+  linmin_opts o;
+  if (opts) o = *opts;
+  else linmin_default_opts(&o);
+  if (o.precision != LINMIN_FP64 && o.precision != LINMIN_MIXED) return LINMIN_EINVAL;
+  if (o.cov_layout < LINMIN_COV_NONE || o.cov_layout > LINMIN_COV_DIAG) return LINMIN_EINVAL;
+  if (o.maxit < 0 || o.max_polish < 0 || !(o.eta > 0.0 && o.eta < 1.0) || !(o.lambda0 > 0.0)) return LINMIN_EINVAL;
+  if (P == 0) return LINMIN_OK;
+  if (!cube || !out_coeffs) return LINMIN_EINVAL;
+  const bool want_cov = out_cov != nullptr && o.cov_layout != LINMIN_COV_NONE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LINMIN_EHIP;
+  if (dev != lib->dev) return LINMIN_EINVAL;
+
+  const Work w = plan(lib, P, o, want_cov);
+  char* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, w.total, st) != hipSuccess) return LINMIN_ENOMEM;
+  auto at = [&](size_t off) -> char* { return off == (size_t)-1 ? nullptr : ws + off; };
+  double* bh = (double*)at(w.bh);
+  double* c = (double*)at(w.c);
+  uint8_t* status = o.status ? o.status : (uint8_t*)at(w.status);
+  int rc = LINMIN_OK;
+
+  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(o.stage_events);
+  auto mark = [&](int i) {
+    if (ev && hipEventRecord(ev[i], st) != hipSuccess) return LINMIN_EHIP;
+    return LINMIN_OK;
+  };
+  // projections bh = Y Wh and c = y^T C^{-1} y
+  rc = mark(0);
+  if (rc == LINMIN_OK) rc = from_launch(lm::launch_gemm_proj_f64(cube, P, lib->L, lib->Wh, lib->ldw, lib->N, bh, c, st));
+  if (rc == LINMIN_OK && lib->Ci) rc = from_launch(lm::launch_quadform_f64(cube, P, lib->L, lib->Ci, lib->L, c, st));
+  if (rc == LINMIN_OK) rc = mark(1);
+  if (rc == LINMIN_OK) {
+    lm::IpmParams prm{};
+    prm.n = lib->N;
+    prm.P = P;
+    prm.bh = bh;
+    prm.c = c;
+    prm.sigma = sigma;
+    prm.gamma = lib->gamma;
+    prm.maxit = o.maxit;
+    prm.max_polish = o.max_polish;
+    prm.tol_mu = o.tol_mu;
+    prm.tol_d = o.tol_d;
+    prm.tol_p = o.tol_p;
+    prm.eta = o.eta;
+    prm.lambda0 = o.lambda0;
+    prm.tau = o.tau;
+    prm.deg_tol = o.deg_tol;
+    prm.mu_switch = o.mu_switch;
+    prm.out_a = out_coeffs;
+    prm.status = status;
+    prm.iters = o.iters;
+    prm.objective = o.objective;
+    prm.dcov = want_cov ? (double*)at(w.dcov) : nullptr;
+    if (o.precision == LINMIN_MIXED) {
+      prm.st_a = (double*)at(w.st_a);
+      prm.st_lam = (double*)at(w.st_lam);
+      prm.st_nu = (double*)at(w.st_nu);
+      prm.st_it = (int32_t*)at(w.st_it);
+      prm.st_flag = (uint8_t*)at(w.st_flag);
+      prm.Gh = lib->Gh32;
+      rc = from_launch(lm::launch_ipm(prm, lm::kStage1, true, st));
+      if (rc == LINMIN_OK) {
+        prm.Gh = lib->Gh64;
+        rc = from_launch(lm::launch_ipm(prm, lm::kStage2, false, st));
+      }
+    } else {
+      prm.Gh = lib->Gh64;
+      rc = from_launch(lm::launch_ipm(prm, lm::kFull, false, st));
+    }
+  }
+  if (rc == LINMIN_OK) rc = mark(2);
+  if (rc == LINMIN_OK && want_cov)
+    rc = from_launch(lm::launch_cov(lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), sigma, lib->gamma, status,
+                                    out_coeffs, o.cov_layout, out_cov, st));
+  if (rc == LINMIN_OK) rc = mark(3);
+  if (hipFreeAsync(ws, st) != hipSuccess && rc == LINMIN_OK) rc = LINMIN_EHIP;
+  return rc;
+}
+
+}  // extern "C"

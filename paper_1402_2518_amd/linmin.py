@@ -1,0 +1,193 @@
+"""Thin Python binding of lib_linmin (``include/linmin.h``) over ctypes.
+
+Argument marshalling only: torch provides device memory and streams, every
+step of the unmixing runs in the library's HIP kernels.  The shared library
+``liblinmin.so`` must have been built (``paper_1402_2518_amd.build``); there
+is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblinmin.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+COV_NONE, COV_FULL, COV_PACKED, COV_DIAG = 0, 1, 2, 3
+PX_MAXIT, PX_NONFINITE, PX_BAD_SIGMA, PX_NOT_PD, PX_DEGENERATE, PX_INEXACT = 1, 2, 4, 8, 16, 32
+N_MAX = 128
+
+EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linmin_workspace_bytes",
+           "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("cov_layout", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("max_polish", ctypes.c_int), ("tol_mu", ctypes.c_double), ("tol_d", ctypes.c_double),
+                ("tol_p", ctypes.c_double), ("eta", ctypes.c_double), ("lambda0", ctypes.c_double),
+                ("tau", ctypes.c_double), ("deg_tol", ctypes.c_double), ("mu_switch", ctypes.c_double),
+                ("status", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("objective", ctypes.c_void_p),
+                ("stage_events", ctypes.c_void_p)]
+
+
+class LinminError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise FileNotFoundError(f"{path} is missing: build it with paper_1402_2518_amd.build.build()")
+        lib = ctypes.CDLL(path)
+        vp = ctypes.c_void_p
+        lib.linmin_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        lib.linmin_default_opts.restype = None
+        lib.linmin_create_library.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        lib.linmin_create_library.restype = ctypes.c_int
+        lib.linmin_unmix.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(Opts), vp]
+        lib.linmin_unmix.restype = ctypes.c_int
+        lib.linmin_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Opts)]
+        lib.linmin_workspace_bytes.restype = ctypes.c_size_t
+        lib.linmin_library_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_double)]
+        lib.linmin_library_info.restype = ctypes.c_int
+        lib.linmin_library_gram.argtypes = [vp, vp]
+        lib.linmin_library_gram.restype = ctypes.c_int
+        lib.linmin_destroy_library.argtypes = [vp]
+        lib.linmin_destroy_library.restype = ctypes.c_int
+        lib.linmin_strerror.argtypes = [ctypes.c_int]
+        lib.linmin_strerror.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().linmin_strerror(int(code)).decode()
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().linmin_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+_PREC = {"fp64": FP64, "mixed": MIXED}
+_COV = {None: COV_NONE, "none": COV_NONE, "full": COV_FULL, "packed": COV_PACKED, "diag": COV_DIAG}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Library:
+    """A reference library (rows of ``S`` are spectra) and optional noise
+    covariance ``C`` (L x L), prepared on the current HIP device."""
+
+    def __init__(self, S: np.ndarray, C: np.ndarray | None = None):
+        S = np.ascontiguousarray(S, dtype=np.float32)
+        if S.ndim != 2:
+            raise ValueError("S must be N x L")
+        self.N, self.L = S.shape
+        Cc = None if C is None else np.ascontiguousarray(C, dtype=np.float64)
+        h = ctypes.c_void_p()
+        rc = load().linmin_create_library(S.ctypes.data_as(ctypes.c_void_p), self.L, self.N,
+                                          None if Cc is None else Cc.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(h))
+        if rc != OK:
+            raise LinminError(rc, "linmin_create_library")
+        self._h = h
+        g = ctypes.c_double()
+        load().linmin_library_info(self._h, None, None, ctypes.byref(g))
+        self.gamma = g.value
+
+    def gram(self) -> np.ndarray:
+        G = np.empty((self.N, self.N))
+        rc = load().linmin_library_gram(self._h, G.ctypes.data_as(ctypes.c_void_p))
+        if rc != OK:
+            raise LinminError(rc, "linmin_library_gram")
+        return G
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().linmin_destroy_library(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, P: int, precision: str = "fp64", cov: str | None = "full") -> int:
+        o = default_opts(precision=_PREC[precision], cov_layout=_COV[cov])
+        return int(load().linmin_workspace_bytes(self._h, int(P), ctypes.byref(o)))
+
+    def unmix_into(self, cube, sigma, out_a, out_cov=None, status=None, iters=None, objective=None,
+                   precision: str = "fp64", cov: str | None = "full", stream=None, events=None, **opts):
+        """Enqueue one unmix on ``stream`` into caller-provided device tensors.
+
+        ``events``: optional four ``torch.cuda.Event(enable_timing=True)``
+        recorded before the projections, the solve, the covariance and after.
+        """
+        import torch
+        if cube.dtype != torch.float32 or not cube.is_contiguous() or cube.dim() != 2:
+            raise ValueError("cube must be a contiguous P x L float32 tensor")
+        P = cube.shape[0]
+        if cube.shape[1] != self.L:
+            raise ValueError("cube has the wrong number of channels")
+        if sigma is not None and (sigma.dtype != torch.float32 or sigma.numel() != P or not sigma.is_contiguous()):
+            raise ValueError("sigma must be a contiguous float32 tensor of P values")
+        o = default_opts(precision=_PREC[precision], cov_layout=_COV[cov], **opts)
+        o.status = None if status is None else status.data_ptr()
+        o.iters = None if iters is None else iters.data_ptr()
+        o.objective = None if objective is None else objective.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        ev_arr = None
+        if events is not None:
+            if len(events) != 4:
+                raise ValueError("events must hold 4 timing events")
+            for e in events:
+                e.record(stream)  # makes sure the underlying HIP event exists
+            ev_arr = (ctypes.c_void_p * 4)(*[ctypes.c_void_p(e.cuda_event) for e in events])
+            o.stage_events = ctypes.cast(ev_arr, ctypes.c_void_p)
+        rc = load().linmin_unmix(self._h, _ptr(cube), int(P), _ptr(sigma), _ptr(out_a), _ptr(out_cov),
+                                 ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise LinminError(rc, "linmin_unmix")
+
+    def unmix(self, cube, sigma=None, precision: str = "fp64", cov: str | None = "full",
+              stream=None, **opts):
+        """Unmix a device cube (P x L float32 torch tensor).
+
+        Returns a dict of device tensors: ``a`` (P x N float64), ``cov`` (per
+        ``cov`` layout, or None), ``status`` (uint8), ``iters`` (int32),
+        ``objective`` (float64).
+        """
+        import torch
+        dev = cube.device
+        P = cube.shape[0]
+        a = torch.empty((P, self.N), dtype=torch.float64, device=dev)
+        shape = {None: None, "none": None, "full": (P, self.N, self.N),
+                 "packed": (P, self.N * (self.N + 1) // 2), "diag": (P, self.N)}[cov]
+        cv = None if shape is None else torch.empty(shape, dtype=torch.float64, device=dev)
+        st = torch.empty(P, dtype=torch.uint8, device=dev)
+        it = torch.empty(P, dtype=torch.int32, device=dev)
+        obj = torch.empty(P, dtype=torch.float64, device=dev)
+        self.unmix_into(cube, sigma, a, cv, st, it, obj, precision=precision, cov=cov, stream=stream, **opts)
+        return {"a": a, "cov": cv, "status": st, "iters": it, "objective": obj}

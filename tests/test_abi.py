@@ -1,0 +1,66 @@
+"""CPU-side checks of the C ABI: the library loads and exports every entry
+point that include/linmin.h declares; the binding mirrors the header's
+constants.  No GPU call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1402_2518_amd import linmin
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "linmin.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(linmin_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("linmin_create_library", "linmin_unmix", "linmin_destroy_library",
+                 "linmin_workspace_bytes", "linmin_strerror", "linmin_default_opts"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(linmin.LIB_PATH):
+        pytest.fail("liblinmin.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(linmin.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(linmin.EXPORTS)
+
+
+def test_constants_match_header():
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"#define (LINMIN_\w+) \(?(-?\d+)u?\)?", txt))
+    assert int(defs["LINMIN_OK"]) == linmin.OK
+    assert int(defs["LINMIN_EINVAL"]) == linmin.EINVAL
+    assert int(defs["LINMIN_EUNSUPPORTED"]) == linmin.EUNSUPPORTED
+    assert int(defs["LINMIN_MIXED"]) == linmin.MIXED
+    assert int(defs["LINMIN_COV_DIAG"]) == linmin.COV_DIAG
+    assert int(defs["LINMIN_PX_INEXACT"]) == linmin.PX_INEXACT
+    assert int(defs["LINMIN_N_MAX"]) == linmin.N_MAX
+
+
+def test_opts_struct_layout():
+    # field order and size of linmin_opts as declared in the header
+    assert ctypes.sizeof(linmin.Opts) == 4 * 4 + 8 * 8 + 4 * 8
+
+
+def test_strerror_and_defaults_without_gpu():
+    lib = linmin.load()
+    assert lib.linmin_strerror(-4).decode().startswith("matrix not")
+    o = linmin.default_opts()
+    assert o.maxit == 100 and o.tol_mu == 1e-13 and o.precision == linmin.FP64
+    h = ctypes.c_void_p()
+    # argument errors are reported before any device work
+    import numpy as np
+    S = np.ones((5, 3), np.float32)
+    assert lib.linmin_create_library(S.ctypes.data_as(ctypes.c_void_p), 3, 5, None, ctypes.byref(h)) == linmin.EINVAL
+    assert lib.linmin_create_library(None, 3, 2, None, ctypes.byref(h)) == linmin.EINVAL
+    assert lib.linmin_unmix(None, None, 0, None, None, None, None, None) == linmin.EINVAL
+    assert lib.linmin_destroy_library(None) == linmin.EINVAL

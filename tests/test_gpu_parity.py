@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Element-by-element comparisons on seeded inputs that span several workgroups
+and a ragged tail, plus the edge cases of the method.  Tolerances (derived in
+the design doc): coefficients 1e-6 absolute for FP64 and 1e-3 for the mixed form
+(its FP64 finishing step brings it to the FP64 level in practice); covariance
+1e-6 relative to its largest entry on certified non-degenerate pixels;
+objective 1e-9 relative (FP64) / 1e-4 relative (mixed).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from paper_1402_2518_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1402_2518_amd import linmin
+    linmin.load()
+    return torch.device("cuda:0")
+
+
+def _gpu(S, X, s, dev, C=None, precision="fp64", cov="full", **opts):
+    from paper_1402_2518_amd import linmin
+    lib = linmin.Library(S, C)
+    Xt = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(dev)
+    st = None if s is None else torch.from_numpy(np.ascontiguousarray(s, np.float32)).to(dev)
+    out = lib.unmix(Xt, st, precision=precision, cov=cov, **opts)
+    torch.cuda.synchronize()
+    res = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+    res["gamma"] = lib.gamma
+    res["sigma"] = np.ones(len(X)) if s is None else np.asarray(s, np.float64)
+    lib.close()
+    return res
+
+
+def _compare(g, r, a_tol=1e-6, cov_tol=1e-6, f_tol=1e-9, check_cov=True):
+    assert np.isfinite(g["a"]).all()
+    da = np.abs(g["a"] - r["a"]).max()
+    assert da <= a_tol, f"max |a_gpu - a_oracle| = {da}"
+    ok = (g["status"] == 0) & (r["status"] == 0)
+    assert ok.mean() > 0.95, np.bincount(g["status"])
+    # statuses agree except for the degenerate flag (a tie-break)
+    mask = ~np.uint8(oracle.DEGENERATE)
+    assert ((g["status"] & mask) == (r["status"] & mask)).mean() > 0.999
+    dF = np.abs(g["objective"] / r["F"] - 1).max()
+    assert dF <= f_tol, f"objective rel err {dF}"
+    if check_cov and g["cov"] is not None:
+        cg, cr = g["cov"][ok], r["cov"][ok]
+        # relative to the pixel's largest entry, floored at the natural scale
+        # s^2 / gamma (a single free coefficient has an all-zero covariance)
+        nat = g["sigma"][ok] ** 2 / g["gamma"]
+        scale = np.maximum(np.abs(cr).reshape(len(cr), -1).max(1), nat)[:, None, None]
+        dc = (np.abs(cg - cr) / scale).max() if len(cg) else 0.0
+        assert dc <= cov_tol, f"cov rel err {dc}"
+    return da
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tiny_workload_parity(dev, precision):
+    _say(f"[gpu] tiny workload 1000 px N=8 {precision}")
+    w = synth.WORKLOADS["tiny"]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    g = _gpu(S, X, s, dev, precision=precision)
+    r = oracle.unmix(S, X, s)
+    _compare(g, r, a_tol=1e-6 if precision == "fp64" else 1e-3,
+             f_tol=1e-9 if precision == "fp64" else 1e-4)
+    # and against enumeration of every active set
+    a_bf, _ = pins.brute_force(pins.gram(S), pins.proj(S, X))
+    assert np.abs(g["a"] - a_bf).max() <= 1e-6
+
+
+@pytest.mark.parametrize("name,n", [("orbital", 3001), ("precision", 403)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workload_samples_parity(dev, name, n, precision):
+    _say(f"[gpu] {name} first {n} px {precision}")
+    w = synth.WORKLOADS[name]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w, p1=n)
+    g = _gpu(S, X, s, dev, precision=precision)
+    r = oracle.unmix(S, X, s)
+    _compare(g, r, a_tol=1e-6 if precision == "fp64" else 1e-3,
+             f_tol=1e-9 if precision == "fp64" else 1e-4)
+    _say(f"[gpu]   iters gpu mean {g['iters'].mean():.2f} oracle {r['iters'].mean():.2f}")
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 16, 24, 31, 40, 48, 57, 64])
+def test_library_sizes(dev, N):
+    _say(f"[gpu] library size N={N}")
+    w = synth.custom_workload(N, max(N, 96), 517, seed=N, n_extra=min(4, N - 1) if N > 1 else 0,
+                              k_max=max(1, min(4, N - 4)) if N > 4 else 1)
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    for precision in ("fp64", "mixed"):
+        g = _gpu(S, X, s, dev, precision=precision)
+        r = oracle.unmix(S, X, s)
+        _compare(g, r, a_tol=1e-6 if precision == "fp64" else 1e-3,
+                 f_tol=1e-9 if precision == "fp64" else 1e-4)
+
+
+def test_ragged_and_empty(dev):
+    _say("[gpu] ragged pixel counts and P=0")
+    w = synth.WORKLOADS["orbital"]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w, p1=40)
+    r = oracle.unmix(S, X, s)
+    for P in (1, 2, 15, 17, 33):
+        g = _gpu(S, X[:P], s[:P], dev)
+        assert np.abs(g["a"] - r["a"][:P]).max() <= 1e-6
+    g = _gpu(S, X[:0], s[:0], dev)
+    assert g["a"].shape == (0, S.shape[0])
+
+
+def test_edge_pixels_are_isolated(dev):
+    _say("[gpu] NaN/Inf spectra and bad sigma")
+    w = synth.WORKLOADS["orbital"]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w, p1=64)
+    X = X.copy()
+    s = s.copy()
+    X[3, 7] = np.nan
+    X[20, 0] = np.inf
+    s[5] = 0.0
+    s[6] = -1.0
+    s[7] = np.nan
+    g = _gpu(S, X, s, dev)
+    r = oracle.unmix(S, X, s)
+    assert g["status"][3] & oracle.NONFINITE and g["status"][20] & oracle.NONFINITE
+    assert np.isnan(g["a"][3]).all() and np.isnan(g["cov"][20]).all()
+    for i in (5, 6, 7):
+        assert g["status"][i] & oracle.BAD_SIGMA
+        assert np.isnan(g["objective"][i]) and np.isnan(g["cov"][i]).all()
+    good = [i for i in range(64) if i not in (3, 20)]
+    assert np.abs(g["a"][good] - r["a"][good]).max() <= 1e-6
+    # neighbours are bit-identical to a run without the bad pixels
+    clean = np.delete(np.arange(64), [3, 20])
+    g2 = _gpu(S, X[clean], s[clean], dev)
+    assert np.array_equal(g2["a"], g["a"][clean])
+
+
+def test_closed_forms_on_gpu(dev):
+    _say("[gpu] identity Gram, N=2 segment, N=1")
+    rng = np.random.default_rng(7)
+    S = pins.disjoint_library(36, 240, rng, equal=True)
+    X = (rng.uniform(0, 1, (300, 240)) * 0.5).astype(np.float32)
+    g = _gpu(S, X, None, dev)
+    c = pins.gram(S)[0, 0]
+    assert np.abs(g["a"] - pins.simplex_project(pins.proj(S, X) / c)).max() <= 1e-10
+    S2 = rng.uniform(0.1, 0.6, (2, 50)).astype(np.float32)
+    X2 = rng.uniform(0.0, 0.7, (100, 50)).astype(np.float32)
+    g2 = _gpu(S2, X2, None, dev)
+    want = np.array([pins.two_endmembers(S2[0].astype(float), S2[1].astype(float), x.astype(float)) for x in X2])
+    assert np.abs(g2["a"] - want).max() <= 1e-9
+    S1 = S2[:1]
+    g1 = _gpu(S1, X2, np.full(100, 0.01, np.float32), dev)
+    assert np.all(g1["a"] == 1.0) and np.all(g1["cov"] == 0.0)
+
+
+def test_covariance_layouts_agree(dev):
+    _say("[gpu] covariance layouts")
+    w = synth.WORKLOADS["orbital"]
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w, p1=200)
+    full = _gpu(S, X, s, dev, cov="full")["cov"]
+    packed = _gpu(S, X, s, dev, cov="packed")["cov"]
+    diag = _gpu(S, X, s, dev, cov="diag")["cov"]
+    N = S.shape[0]
+    il = np.tril_indices(N)
+    assert np.array_equal(packed, full[:, il[0], il[1]])
+    assert np.array_equal(diag, np.diagonal(full, axis1=1, axis2=2))
+    g = _gpu(S, X, s, dev, cov=None)
+    assert g["cov"] is None
+
+
+def test_noise_covariance(dev):
+    _say("[gpu] full noise covariance (eqs. 5-6)")
+    rng = np.random.default_rng(23)
+    N, L = 12, 100
+    S = synth.mineral_spectra(N, L, rng).astype(np.float32)
+    Q = rng.standard_normal((L, L))
+    C = (Q @ Q.T / L + np.diag(rng.uniform(0.5, 2.0, L))) * 1e-4
+    X = (rng.dirichlet(np.ones(N), 300) @ S.astype(float) + 0.01 * rng.standard_normal((300, L))).astype(np.float32)
+    s = rng.uniform(0.5, 2.0, 300).astype(np.float32)
+    g = _gpu(S, X, s, dev, C=C)
+    r = oracle.unmix(S, X, s, C=C)
+    _compare(g, r)
+
+
+def test_noise_free_exact_recovery(dev):
+    _say("[gpu] dyadic exact recovery")
+    rng = np.random.default_rng(11)
+    N, L = 8, 64
+    S = (rng.integers(1, 256, (N, L)) / 256.0).astype(np.float32)
+    A = np.zeros((40, N))
+    for p in range(40):
+        idx = rng.choice(N, 3, replace=False)
+        A[p, idx] = (0.5, 0.25, 0.25)
+    X = (A @ S.astype(np.float64)).astype(np.float32)
+    g = _gpu(S, X, np.full(40, 0.01, np.float32), dev)
+    assert np.abs(g["a"] - A).max() <= 1e-9
