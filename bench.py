@@ -102,7 +102,7 @@ def main():
     achieved = flops / (ipm_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-            "kernel": "ipm_kernel<double,36,16,full>", "kernel_ms": ipm_ms,
+            "kernel": "ipm_tile_kernel<9,full> (FP64 4x4x4 MFMA tiles)", "kernel_ms": ipm_ms,
             "flops_per_launch": flops, "mean_iters": float(it64.mean())}
 
     result = {

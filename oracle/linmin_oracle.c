@@ -326,9 +326,12 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
         double ratio = mu_aff / mu;
         double sigma = ratio * ratio * ratio;
 
-        /* corrector (centring + second-order term) */
+        /* corrector (centring + second-order term); the second-order term is
+         * dropped when the affine step is short, which stops Mehrotra's
+         * heuristic from cycling (Salahi, Peng & Terlaky 2008) */
+        const double soc = t_aff >= 0.1 ? 1.0 : 0.0;
         for (int i = 0; i < N; ++i)
-            W->rc[i] = a[i] * lam[i] + W->da_aff[i] * W->dl_aff[i] - sigma * mu;
+            W->rc[i] = a[i] * lam[i] + soc * W->da_aff[i] * W->dl_aff[i] - sigma * mu;
         newton_dir(W, N, a, rd, rp, su, W->rc, W->da, W->dl, &dnu);
         double t = fmin(max_step(a, W->da, N), max_step(lam, W->dl, N));
         double alpha = o->eta * t;

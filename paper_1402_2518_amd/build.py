@@ -28,6 +28,11 @@ def shapes():
     return re.findall(r"^LM_SHAPE\((\w+),\s*(\d+),\s*(\d+)\)", txt, re.M)
 
 
+def tiles():
+    txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
+    return re.findall(r"^LM_TILE\((\d+)\)", txt, re.M)
+
+
 def _compile(src, obj, extra=()):
     cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,6 +49,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for t, nc, g in shapes():
         units.append((os.path.join(CSRC, "ipm.hip"), os.path.join(BUILD, f"ipm_{t}_{nc}_{g}.o"),
                       (f"-DLM_T={t}", f"-DLM_NC={nc}", f"-DLM_G={g}")))
+    for t in tiles():
+        units.append((os.path.join(CSRC, "ipm_tile.hip"), os.path.join(BUILD, f"ipm_tile_{t}.o"),
+                      (f"-DLM_TILE_T={t}",)))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_compile, s, o, e) for s, o, e in units]

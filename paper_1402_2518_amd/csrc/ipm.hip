@@ -21,6 +21,7 @@
 //   r_d = Gh a - bh - lambda + nu 1,  r_p = 1^T a - 1,  mu = a^T lambda / n
 //   H = Gh + diag(lambda / a)
 //   predictor rc = a*lambda; corrector rc = a*lambda + da_aff*dl_aff - sigma mu
+//   (the second-order term is dropped when the affine step is below 0.1)
 //   [H 1; 1^T 0] [da; dnu] = [-r_d - rc/a; -r_p],  dl = -rc/a - D da
 // Finishing step: free set F = {a_i > lambda_i}; solve the problem with
 // a_A = 0 exactly (diagonal BIG on A), check a_F >= -tau and
@@ -423,10 +424,12 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
         });
         const T ratio = (gsum<G>(smu) / T(n)) / mu;
         sig = ratio * ratio * ratio;
-        // corrector right-hand side; dla <- rc / a
+        // corrector right-hand side; dla <- rc / a.  The second-order term
+        // is dropped after a short affine step (guards against cycling).
+        const T soc = st_aff >= T(0.1) ? T(1) : T(0);
         static_for<0, S>([&](auto ss) {
           constexpr int s = decltype(ss)::value;
-          const T rc = fmaT(x[s], dla[s], a[s] * lam[s]) - sig * mu;
+          const T rc = fmaT(soc * x[s], dla[s], a[s] * lam[s]) - sig * mu;
           dla[s] = vm[s] ? rc / a[s] : T(0);
           x[s] = vm[s] ? -rd[s] - dla[s] : T(0);
         });

@@ -1,29 +1,66 @@
 // ipm_dispatch.cpp -- choose the compiled interior-point shape for a library.
+#include <stdlib.h>
+#include <string.h>
+
 #include "kernels.h"
 
 namespace lm {
 
 #define LM_SHAPE(t, nc, g) int ipm_entry_##t##_##nc##_##g(const IpmParams& p, int mode, hipStream_t st);
+#define LM_TILE(t) int ipm_tile_entry_##t(const IpmParams& p, int mode, hipStream_t st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
+#undef LM_TILE
 
 int ipm_shape_nc(int n) {
   int best = -1;
 #define LM_SHAPE(t, nc, g) \
   if (nc >= n && (best < 0 || nc < best)) best = nc;
+#define LM_TILE(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
+#undef LM_TILE
   return best;
+}
+
+// FP64 kernel family: the matrix-core tile kernel where a tile shape exists
+// for NC, else the lane-group kernel.  LINMIN_FP64_KERNEL=valu forces the
+// lane-group kernel (both are complete implementations; the switch exists to
+// compare them).
+static bool use_tile(int nc) {
+  static int forced = -1;
+  if (forced < 0) {
+    const char* e = getenv("LINMIN_FP64_KERNEL");
+    forced = (e && strcmp(e, "valu") == 0) ? 1 : 0;
+  }
+  if (forced == 1 || nc % 4) return false;
+  bool have = false;
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t) have |= (4 * t == nc);
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+  return have;
 }
 
 int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st) {
   if (p.P <= 0) return 0;
   const int nc = ipm_shape_nc(p.n);
   if (nc < 0) return -5;
-#define LM_SHAPE(t, nc_, g)                                              \
-  if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return ipm_entry_##t##_##nc_##_##g(p, mode, st);
+  if (!fp32 && use_tile(nc)) {
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t) \
+    if (4 * t == nc) return ipm_tile_entry_##t(p, mode, st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
+#undef LM_TILE
+  }
+#define LM_SHAPE(t, nc_, g)                                              \
+  if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return ipm_entry_##t##_##nc_##_##g(p, mode, st);
+#define LM_TILE(t)
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
   return -5;
 }
 

@@ -114,6 +114,17 @@ def test_library_sizes(dev, N):
                  f_tol=1e-9 if precision == "fp64" else 1e-4)
 
 
+def test_cycling_pixels_converge(dev):
+    _say("[gpu] orbital pixels that make plain Mehrotra cycle")
+    from test_oracle import cycling_pixels
+    S, X, s = cycling_pixels()
+    for precision in ("fp64", "mixed"):
+        g = _gpu(S, X, s, dev, precision=precision)
+        r = oracle.unmix(S, X, s)
+        assert (g["status"] & ~np.uint8(oracle.DEGENERATE) == 0).all(), g["status"]
+        assert np.abs(g["a"] - r["a"]).max() <= 1e-6
+
+
 def test_ragged_and_empty(dev):
     _say("[gpu] ragged pixel counts and P=0")
     w = synth.WORKLOADS["orbital"]

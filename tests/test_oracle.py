@@ -53,6 +53,26 @@ def test_kkt_on_workloads(oracle_lib, name, n):
     assert r["iters"].max() < 40
 
 
+# Orbital-cube pixels on which plain Mehrotra steps cycle (mu bouncing between
+# 1e-9 and 4e-9); the corrector safeguard must let them converge.
+CYCLING_PIXELS = (37492, 254619, 274661, 418662)
+
+
+def cycling_pixels():
+    w = synth.WORKLOADS["orbital"]
+    S = synth.make_library(w)
+    parts = [synth.make_cube(w, S, p0=p, p1=p + 1) for p in CYCLING_PIXELS]
+    return S, np.concatenate([x for x, _ in parts]), np.concatenate([s for _, s in parts])
+
+
+def test_no_cycling_on_known_pixels(oracle_lib):
+    S, X, s = cycling_pixels()
+    r = _run(oracle_lib, S, X, s, cov=False)
+    assert (r["status"] & ~np.uint8(oracle_lib.DEGENERATE) == 0).all(), r["status"]
+    assert r["iters"].max() < 30
+    assert pins.natural_residual(pins.gram(S), pins.proj(S, X), r["a"]).max() <= 1e-10
+
+
 # --------------------------------------------------------- brute force ----
 
 def test_brute_force_tiny_workload(oracle_lib):

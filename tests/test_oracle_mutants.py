@@ -24,6 +24,7 @@ MUTANTS = {
     "finishing step accepts any partition": ("if (worst_a < 0 && worst_l < 0) {", "if (1) {"),
     "renormalised pixel uses Lc transposed": ("for (int l = j; l < L; ++l) s += (double)x[l] * Lc[l * L + j];",
                                               "for (int l = j; l < L; ++l) s += (double)x[l] * Lc[j * L + l];"),
+    "corrector safeguard removed": ("const double soc = t_aff >= 0.1 ? 1.0 : 0.0;", "const double soc = 1.0;"),
     "gram transposed index": ("for (int j = 0; j < N; ++j) s += Gh[i * N + j] * a[j];",
                               "for (int j = 0; j < N; ++j) s += Gh[i * N + j] * a[i];"),
 }
@@ -50,6 +51,10 @@ def pin_failures(lib):
     check("kkt", lambda: pins.natural_residual(G, B, r["a"]).max() <= 1e-10)
     bad = oracle.MAXIT | oracle.NOT_PD | oracle.INEXACT
     check("converged and certified", lambda: not (r["status"] & bad).any() and r["iters"].max() < 40)
+    from test_oracle import cycling_pixels
+    Sc_, Xc_, sc_ = cycling_pixels()
+    rcy = oracle.unmix(Sc_, Xc_, sc_, cov=False, lib=lib)
+    check("no cycling", lambda: not (rcy["status"] & bad).any())
     check("sum", lambda: np.abs(r["a"].sum(1) - 1).max() <= 1e-13)
     res = X.astype(float) - r["a"] @ S.astype(float)
     check("objective", lambda: np.abs(r["F"] / ((res ** 2).sum(1) / s.astype(float) ** 2) - 1).max() <= 1e-8)
