@@ -40,6 +40,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=200,
+                    help="sequential whole-cube calls behind the p50/p99 latency")
+    ap.add_argument("--variants", type=int, default=5,
+                    help="timed calls for each covariance layout / shard-size variant (0 = skip)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "lib_linmin runs on one GPU: pixels are independent and this build "
@@ -67,17 +73,29 @@ def main():
     iters = torch.empty(P, dtype=torch.int32, device=dev)
     obj = torch.empty(P, dtype=torch.float64, device=dev)
 
-    def run(precision, steps, warmup, a_out):
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src_t = torch.empty(nb, dtype=torch.uint8, device=dev).fill_(1)
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nb} bytes read, {nb} bytes written", file=sys.stderr, flush=True)
+        del src_t, dst_t
+
+    def run(precision, steps, warmup, a_out, cov="full", npix=P):
+        X_, s_ = Xd[:npix], sd[:npix]
+        a_, st_, it_, ob_ = a_out[:npix], status[:npix], iters[:npix], obj[:npix]
+        c_ = out_cov[:npix] if cov == "full" else (out_cov.view(-1)[:npix * N].view(npix, N) if cov == "diag" else None)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         with torch.cuda.stream(stream):
             for _ in range(warmup):
-                lib.unmix_into(Xd, sd, a_out, out_cov, status, iters, obj, precision=precision,
-                               cov="full", stream=stream)
+                lib.unmix_into(X_, s_, a_, c_, st_, it_, ob_, precision=precision, cov=cov, stream=stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for k in range(steps):
-                lib.unmix_into(Xd, sd, a_out, out_cov, status, iters, obj, precision=precision,
-                               cov="full", stream=stream, events=evs[k])
+                lib.unmix_into(X_, s_, a_, c_, st_, it_, ob_, precision=precision, cov=cov, stream=stream,
+                               events=evs[k])
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
         stage = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
@@ -95,6 +113,29 @@ def main():
     itmx = iters.cpu().numpy()
     print(f"# mixed: {wallmx / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
     mix_err = float((out_a_mix - a64).abs().max().item())
+
+    # single-cube latency: sequential calls, device time of each call
+    lat = {}
+    if args.latency_calls > 0:
+        for prec, buf in (("fp64", out_a), ("mixed", out_a_mix)):
+            _, stl = run(prec, args.latency_calls, 1, buf)
+            lat[prec] = {"p50": float(np.percentile(stl[:, 3], 50)), "p99": float(np.percentile(stl[:, 3], 99)),
+                         "calls": int(args.latency_calls)}
+        print(f"# latency: {lat}", file=sys.stderr, flush=True)
+    # other covariance layouts and one GPU's share of an 8-way pixel split
+    variants = {}
+    if args.variants > 0:
+        for prec, buf in (("fp64", out_a), ("mixed", out_a_mix)):
+            for cov in ("diag", "none"):
+                wv, _ = run(prec, args.variants, 1, buf, cov=cov)
+                variants[f"{prec}_cov_{cov}"] = {"pixels_per_s": P * args.variants / wv,
+                                                 "ms_per_call": wv / args.variants * 1e3}
+        shard = P // 8
+        for prec, buf in (("fp64", out_a), ("mixed", out_a_mix)):
+            wv, _ = run(prec, args.variants, 1, buf, npix=shard)
+            variants[f"{prec}_cov_full_P{shard}"] = {"pixels_per_s": shard * args.variants / wv,
+                                                     "ms_per_call": wv / args.variants * 1e3}
+        print(f"# variants: {variants}", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (interior-point solve)
     ipm_ms = float(np.mean(st64[:, 1]))
@@ -121,16 +162,18 @@ def main():
         "config": {"workload": "orbital cube: N=36 (32 minerals + 4 extras), L=240, P=128x4096=524288, "
                                "fp32 reflectance, sigma~U[0.002,0.01], FP64 solve, full covariance",
                    "global_batch": P, "seq_len": w.L, "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(st64[:, 3], 50)), "p99": float(np.percentile(st64[:, 3], 99)),
-                       "samples": int(len(st64))},
+        "latency_ms": lat.get("fp64", {"p50": float(np.percentile(st64[:, 3], 50)),
+                                       "p99": float(np.percentile(st64[:, 3], 99)), "calls": int(len(st64))}),
         "stages_ms": {"projection": float(np.mean(st64[:, 0])), "ipm": ipm_ms,
                       "covariance": float(np.mean(st64[:, 2]))},
         "mixed": {"value": P * args.steps / wallmx, "ms_per_step": wallmx / args.steps * 1e3,
                   "stages_ms": {"projection": float(np.mean(stmx[:, 0])), "ipm": float(np.mean(stmx[:, 1])),
                                 "covariance": float(np.mean(stmx[:, 2]))},
-                  "latency_ms": {"p50": float(np.percentile(stmx[:, 3], 50)),
-                                 "p99": float(np.percentile(stmx[:, 3], 99))},
+                  "latency_ms": lat.get("mixed", {"p50": float(np.percentile(stmx[:, 3], 50)),
+                                                  "p99": float(np.percentile(stmx[:, 3], 99)),
+                                                  "calls": int(len(stmx))}),
                   "max_abs_coeff_diff_vs_fp64": mix_err, "mean_iters": float(itmx.mean())},
+        "variants": variants,
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stat64, return_counts=True))},
         "roofline": roof,
     }

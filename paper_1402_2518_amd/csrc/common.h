@@ -123,6 +123,18 @@ __device__ __forceinline__ T gbcast(T v, int t) {
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Reciprocal from the hardware estimate refined by Newton steps (one for
+// float, two for double): a division that does not need IEEE rounding.
+__device__ __forceinline__ float rcpT(float x) {
+  float y = __builtin_amdgcn_rcpf(x);
+  return y * fmaT(-x, y, 2.0f);
+}
+__device__ __forceinline__ double rcpT(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fmaT(-x, y, 2.0);
+  return y * fmaT(-x, y, 2.0);
+}
+
 // Orders this wave's LDS writes before its later LDS reads.
 __device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 

@@ -139,7 +139,7 @@ struct Px {
         const T cb = buf[NC];
         const bool bad = !(d > T(0)) || !finite(d);
         notpd |= bad;
-        const T rcp = bad ? T(1) : T(1) / d;
+        const T rcp = bad ? T(1) : rcpT(d);
         dinv[sk] = (t == tk) ? rcp : dinv[sk];
         const T lb = cb * rcp;
         dN -= lb * cb;

@@ -168,9 +168,12 @@ struct Tile {
           bad = true;
           d = 1.0;
         }
-        const double s = __builtin_sqrt(d);
-        l[j][j] = s;
-        r[j] = 1.0 / s;
+        // 1/sqrt(d): hardware estimate refined by two Newton steps
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * fmaT(-0.5 * d, y * y, 1.5);
+        y = y * fmaT(-0.5 * d, y * y, 1.5);
+        l[j][j] = d * y;
+        r[j] = y;
 #pragma unroll
         for (int i = j + 1; i < 4; ++i) {
           double v = m[i * 4 + j];
@@ -245,7 +248,7 @@ struct Tile {
 };
 
 template <int T, int MODE>
-__global__ __launch_bounds__(256) void ipm_tile_kernel(IpmParams prm) {
+__global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   using TL = Tile<T>;
   constexpr int NP = TL::NP;
   constexpr int C = TL::C;

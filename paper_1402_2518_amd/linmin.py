@@ -152,6 +152,26 @@ class Library:
             raise ValueError("cube has the wrong number of channels")
         if sigma is not None and (sigma.dtype != torch.float32 or sigma.numel() != P or not sigma.is_contiguous()):
             raise ValueError("sigma must be a contiguous float32 tensor of P values")
+        N = self.N
+        per = {None: 0, "none": 0, "full": N * N, "packed": N * (N + 1) // 2, "diag": N}[cov]
+
+        def _check(t, name, dtype, numel):
+            if t is None:
+                return
+            if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel or t.device != cube.device:
+                raise ValueError(f"{name} must be a contiguous {dtype} tensor of {numel} values on {cube.device}")
+
+        if out_a is None:
+            raise ValueError("out_a is required")
+        _check(out_a, "out_a", torch.float64, P * N)
+        if per == 0 and out_cov is not None:
+            raise ValueError(f"out_cov given but cov={cov!r}")
+        if per > 0 and out_cov is None:
+            raise ValueError(f"cov={cov!r} needs out_cov")
+        _check(out_cov, "out_cov", torch.float64, P * per)
+        _check(status, "status", torch.uint8, P)
+        _check(iters, "iters", torch.int32, P)
+        _check(objective, "objective", torch.float64, P)
         o = default_opts(precision=_PREC[precision], cov_layout=_COV[cov], **opts)
         o.status = None if status is None else status.data_ptr()
         o.iters = None if iters is None else iters.data_ptr()
