@@ -10,8 +10,8 @@ namespace lm {
 // ---------------------------------------------------------------------------
 // Lane moves inside a group.  Groups of G consecutive lanes (G = 1, 2, 4, 8,
 // 16, 32) work on one pixel; every cross-lane operation below stays inside
-// the group (DPP within a 16-lane row, one xor-16 shuffle for 32-lane
-// groups), so it never mixes pixels.
+// the group (DPP within a 16-lane row, one row swap for 32-lane groups), so
+// it never mixes pixels.
 // ---------------------------------------------------------------------------
 constexpr int qp(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
 constexpr int kRowMirror = 0x140;      // lane i <- lane 15-i within a row
@@ -37,12 +37,51 @@ __device__ __forceinline__ int dpp(int v) {
   return dpp_i32<CTRL>(v);
 }
 
+// Row exchanges without LDS (v_permlane16_swap / v_permlane32_swap).  Rows
+// are the four 16-lane groups of the wave.  pair<16>(v) returns, at this
+// lane's position inside its row, v of the even row of its row pair (rows
+// 0/1, 2/3) in .lo and v of the odd row in .hi; pair<32>(v) returns v of the
+// lower 32 lanes in .lo and of the upper 32 in .hi.  Combining .lo and .hi
+// with a commutative operation gives the same bits on both partner lanes.
+template <typename T>
+struct Pair {
+  T lo, hi;
+};
+template <int W>
+__device__ __forceinline__ Pair<uint32_t> pair_u32(uint32_t v) {
+  static_assert(W == 16 || W == 32, "row pairs are 16 or 32 lanes apart");
+  if constexpr (W == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return {r[0], r[1]};
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return {r[0], r[1]};
+  }
+}
+template <int W>
+__device__ __forceinline__ Pair<int> pair(int v) {
+  const Pair<uint32_t> r = pair_u32<W>((uint32_t)v);
+  return {(int)r.lo, (int)r.hi};
+}
+template <int W>
+__device__ __forceinline__ Pair<float> pair(float v) {
+  const Pair<uint32_t> r = pair_u32<W>(__float_as_uint(v));
+  return {__uint_as_float(r.lo), __uint_as_float(r.hi)};
+}
+template <int W>
+__device__ __forceinline__ Pair<double> pair(double v) {
+  const Pair<uint32_t> l = pair_u32<W>((uint32_t)__double2loint(v));
+  const Pair<uint32_t> h = pair_u32<W>((uint32_t)__double2hiint(v));
+  return {__hiloint2double((int)h.lo, (int)l.lo), __hiloint2double((int)h.hi, (int)l.hi)};
+}
+
 // Sum / max / min over the group; every lane of the group gets the same bits
 // (each butterfly step adds the same two operands on both partner lanes).
 // lane i <- lane i^16 (crosses DPP rows; only used by 32-lane groups)
 template <typename T>
 __device__ __forceinline__ T xor16(T v) {
-  return __shfl_xor(v, 16);
+  const Pair<T> p = pair<16>(v);
+  return ((__lane_id() >> 4) & 1) ? p.lo : p.hi;
 }
 
 template <int G, typename T>
@@ -52,7 +91,10 @@ __device__ __forceinline__ T gsum(T v) {
   if constexpr (G >= 4) v += dpp<qp(2, 3, 0, 1)>(v);
   if constexpr (G >= 8) v += dpp<kRowHalfMirror>(v);
   if constexpr (G >= 16) v += dpp<kRowMirror>(v);
-  if constexpr (G >= 32) v += xor16(v);
+  if constexpr (G >= 32) {
+    const Pair<T> p = pair<16>(v);
+    v = p.lo + p.hi;
+  }
   return v;
 }
 template <int G, typename T>
@@ -61,7 +103,10 @@ __device__ __forceinline__ T gmax(T v) {
   if constexpr (G >= 4) v = fmax(v, dpp<qp(2, 3, 0, 1)>(v));
   if constexpr (G >= 8) v = fmax(v, dpp<kRowHalfMirror>(v));
   if constexpr (G >= 16) v = fmax(v, dpp<kRowMirror>(v));
-  if constexpr (G >= 32) v = fmax(v, xor16(v));
+  if constexpr (G >= 32) {
+    const Pair<T> p = pair<16>(v);
+    v = fmax(p.lo, p.hi);
+  }
   return v;
 }
 template <int G, typename T>
@@ -70,7 +115,10 @@ __device__ __forceinline__ T gmin(T v) {
   if constexpr (G >= 4) v = fmin(v, dpp<qp(2, 3, 0, 1)>(v));
   if constexpr (G >= 8) v = fmin(v, dpp<kRowHalfMirror>(v));
   if constexpr (G >= 16) v = fmin(v, dpp<kRowMirror>(v));
-  if constexpr (G >= 32) v = fmin(v, xor16(v));
+  if constexpr (G >= 32) {
+    const Pair<T> p = pair<16>(v);
+    v = fmin(p.lo, p.hi);
+  }
   return v;
 }
 template <int G>
@@ -79,7 +127,10 @@ __device__ __forceinline__ int gmin_i(int v) {
   if constexpr (G >= 4) v = min(v, dpp<qp(2, 3, 0, 1)>(v));
   if constexpr (G >= 8) v = min(v, dpp<kRowHalfMirror>(v));
   if constexpr (G >= 16) v = min(v, dpp<kRowMirror>(v));
-  if constexpr (G >= 32) v = min(v, xor16(v));
+  if constexpr (G >= 32) {
+    const Pair<int> p = pair<16>(v);
+    v = min(p.lo, p.hi);
+  }
   return v;
 }
 template <int G>
@@ -88,7 +139,10 @@ __device__ __forceinline__ int gor_i(int v) {
   if constexpr (G >= 4) v |= dpp<qp(2, 3, 0, 1)>(v);
   if constexpr (G >= 8) v |= dpp<kRowHalfMirror>(v);
   if constexpr (G >= 16) v |= dpp<kRowMirror>(v);
-  if constexpr (G >= 32) v |= xor16(v);
+  if constexpr (G >= 32) {
+    const Pair<int> p = pair<16>(v);
+    v = p.lo | p.hi;
+  }
   return v;
 }
 
@@ -117,6 +171,14 @@ __device__ __forceinline__ T gbcast(T v, int t) {
     }
     return v;
   }
+}
+
+// Finite (neither infinite nor NaN).  A class test, not v - v == 0: with
+// floating-point contraction the compiler may fuse the subtraction with the
+// multiply that produced v, which yields v's rounding error instead of zero.
+template <typename T>
+__device__ __forceinline__ bool isfin(T v) {
+  return __builtin_isfinite(v);
 }
 
 // Fused multiply-add in the operand precision (no promotion of float).

@@ -40,13 +40,13 @@ __global__ __launch_bounds__(256) void cov_kernel(int n, int64_t P, const double
     double* o = out + p * per;
     bool bad = status && (status[p] & (kPxNonfinite | kPxBadSigma));
     const double s = sigma ? (double)sigma[p] : 1.0;
-    if (!(s > 0.0) || !(s == s) || s - s != 0.0) bad = true;
+    if (!(s > 0.0) || !isfin(s)) bad = true;
     // included set by ballot compaction
     int m = 0;
     for (int base = 0; base < n; base += 64) {
       const int i = base + lane;
       const double di = i < n ? d[i] : 0.0;
-      const bool inc = i < n && di == di && di - di == 0.0;
+      const bool inc = i < n && isfin(di);
       const uint64_t mask = __builtin_amdgcn_ballot_w64(inc);
       const int at = m + __builtin_popcountll(mask & below);
       if (i < n) pos[i] = inc ? at : -1;

@@ -53,7 +53,7 @@ __device__ __forceinline__ void static_for_rev(F&& f) {
 
 template <typename T>
 __device__ __forceinline__ bool finite(T v) {
-  return v == v && v - v == T(0);
+  return isfin(v);
 }
 
 // One pixel's factor/solve machinery on its group of G lanes.

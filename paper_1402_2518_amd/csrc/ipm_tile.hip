@@ -13,9 +13,13 @@
 // A tile X is kept "stored": lane (x, z) holds X[z][x].  Then one register
 // is A = X and B = X^T at once, and
 //     mfma(stored P, stored Q, stored R) = stored(Q P^T + R),
-// so the Cholesky trailing update H_IJ -= L_IK L_JK^T is one MFMA on the
-// stored tiles with no data movement, and the panel is L_IK = H_IK W^T with
-// W = inverse of the 4x4 diagonal factor.  Vectors that feed the MFMA use the
+// so the trailing update of a block factorisation, H_IJ -= L_IK H_JK^T, is
+// one MFMA on stored tiles with no data movement.  The Newton matrix is
+// factored as a block L D L^T (unit lower L, 4x4 diagonal blocks D_K): the
+// panel is L_IK = H_IK D_K^{-1}, and D_K^{-1} comes from a redundant 4x4
+// L D L^T on every lane of the block after an all-gather by quad broadcasts
+// and row swaps, so there are no square roots and no LDS round trips on the
+// factorisation's critical path.  Vectors that feed the MFMA use the
 // "x layout": lane (x, z) holds element 4I + x of right-hand side z, so up
 // to four right-hand sides ride along (the solve carries u = H^{-1} 1 next to
 // the Newton right-hand side).  Elementwise work uses a compact layout: lane
@@ -35,46 +39,44 @@ __device__ __forceinline__ double qb(double v) {
   return dpp<qp(R, R, R, R)>(v);
 }
 
-// sum over the 16 lanes of a block (same bits on every lane)
+// Reductions over the 16 lanes of a block (same bits on every lane): a quad
+// butterfly with DPP, then the row pair (x ^ 1) and the half-wave pair
+// (x ^ 2) through row swaps.
+template <typename T, typename Op>
+__device__ __forceinline__ T bred(T v, Op op) {
+  v = op(v, dpp<qp(1, 0, 3, 2)>(v));
+  v = op(v, dpp<qp(2, 3, 0, 1)>(v));
+  Pair<T> p = pair<16>(v);
+  v = op(p.lo, p.hi);
+  p = pair<32>(v);
+  return op(p.lo, p.hi);
+}
 __device__ __forceinline__ double bsum(double v) {
-  v += dpp<qp(1, 0, 3, 2)>(v);
-  v += dpp<qp(2, 3, 0, 1)>(v);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+  return bred(v, [](double a, double b) { return a + b; });
 }
 __device__ __forceinline__ double bmin(double v) {
-  v = fmin(v, dpp<qp(1, 0, 3, 2)>(v));
-  v = fmin(v, dpp<qp(2, 3, 0, 1)>(v));
-  v = fmin(v, __shfl_xor(v, 16));
-  v = fmin(v, __shfl_xor(v, 32));
-  return v;
+  return bred(v, [](double a, double b) { return fmin(a, b); });
 }
 __device__ __forceinline__ double bmax(double v) {
-  v = fmax(v, dpp<qp(1, 0, 3, 2)>(v));
-  v = fmax(v, dpp<qp(2, 3, 0, 1)>(v));
-  v = fmax(v, __shfl_xor(v, 16));
-  v = fmax(v, __shfl_xor(v, 32));
-  return v;
+  return bred(v, [](double a, double b) { return fmax(a, b); });
 }
 __device__ __forceinline__ int bmin_i(int v) {
-  v = min(v, dpp<qp(1, 0, 3, 2)>(v));
-  v = min(v, dpp<qp(2, 3, 0, 1)>(v));
-  v = min(v, __shfl_xor(v, 16));
-  v = min(v, __shfl_xor(v, 32));
-  return v;
+  return bred(v, [](int a, int b) { return min(a, b); });
 }
 __device__ __forceinline__ int bor_i(int v) {
-  v |= dpp<qp(1, 0, 3, 2)>(v);
-  v |= dpp<qp(2, 3, 0, 1)>(v);
-  v |= __shfl_xor(v, 16);
-  v |= __shfl_xor(v, 32);
-  return v;
+  return bred(v, [](int a, int b) { return a | b; });
+}
+
+// Reciprocal to about single precision squared (one Newton step), for
+// step-to-boundary ratios, which only need a few digits.
+__device__ __forceinline__ double rcp1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return y * fmaT(-x, y, 2.0);
 }
 
 template <typename T>
 __device__ __forceinline__ bool fin(T v) {
-  return v == v && v - v == T(0);
+  return isfin(v);
 }
 
 template <int T>
@@ -86,9 +88,10 @@ struct Tile {
 
   int x, z, blk;            // lane coordinates
   const double* sG;         // LDS, NP x NP scaled Gram
-  double* xch;              // LDS, 32 doubles of this pixel
-  double H[NT];             // stored tiles (lower), then the Cholesky factor
-  double W[T], WT[T];       // inverse diagonal factors, stored and transposed
+  double* xch;              // LDS, 16 doubles of this pixel (tile exchange)
+  // Stored tiles of the lower triangle.  After factor(): block L D L^T with
+  // unit lower L; H[id(K, K)] = D_K^{-1}, H[id(I, K)] = -L_IK (I > K).
+  double H[NT];
   bool notpd;
 
   // compact -> x layout (every right-hand side slot gets the same vector)
@@ -141,107 +144,92 @@ struct Tile {
     });
   }
 
-  // tiled right-looking Cholesky H = L L^T
+  // -M^{-1}[z][x] for the symmetric 4x4 tile M held in stored form (lane
+  // (x, z) holds M[z][x]).  The block's 16 lanes exchange the tile through
+  // LDS, factor it redundantly as L diag(d) L^T (unit lower L), and each lane
+  // solves M y = -e_x for its own column, keeping entry z.
+  __device__ __forceinline__ double ninv4(double h, bool& bad) const {
+    xch[z * 4 + x] = h;
+    lds_sync();
+    const double m00 = xch[0], m10 = xch[4], m11 = xch[5], m20 = xch[8], m21 = xch[9];
+    const double m22 = xch[10], m30 = xch[12], m31 = xch[13], m32 = xch[14], m33 = xch[15];
+    const double d0 = m00;
+    const double r0 = rcpT(d0);
+    const double l10 = m10 * r0, l20 = m20 * r0, l30 = m30 * r0;
+    const double d1 = fmaT(-l10, m10, m11);
+    const double r1 = rcpT(d1);
+    const double t21 = fmaT(-l20, m10, m21), t31 = fmaT(-l30, m10, m31);
+    const double l21 = t21 * r1, l31 = t31 * r1;
+    const double d2 = fmaT(-l21, t21, fmaT(-l20, m20, m22));
+    const double r2 = rcpT(d2);
+    const double t32 = fmaT(-l31, t21, fmaT(-l30, m20, m32));
+    const double l32 = t32 * r2;
+    const double d3 = fmaT(-l32, t32, fmaT(-l31, t31, fmaT(-l30, m30, m33)));
+    const double r3 = rcpT(d3);
+    const double dmin = fmin(fmin(d0, d1), fmin(d2, d3));
+    bad |= !(dmin > 0.0) || !fin(d0 + d1 + d2 + d3);
+    // L v = -e_x, y = L^{-T} diag(r) v
+    const double e0 = x == 0 ? -1.0 : 0.0, e1 = x == 1 ? -1.0 : 0.0;
+    const double e2 = x == 2 ? -1.0 : 0.0, e3 = x == 3 ? -1.0 : 0.0;
+    const double v1 = fmaT(-l10, e0, e1);
+    const double v2 = fmaT(-l21, v1, fmaT(-l20, e0, e2));
+    const double v3 = fmaT(-l32, v2, fmaT(-l31, v1, fmaT(-l30, e0, e3)));
+    const double y3 = v3 * r3;
+    const double y2 = fmaT(-l32, y3, v2 * r2);
+    const double y1 = fmaT(-l31, y3, fmaT(-l21, y2, v1 * r1));
+    const double y0 = fmaT(-l30, y3, fmaT(-l20, y2, fmaT(-l10, y1, e0 * r0)));
+    return z == 0 ? y0 : (z == 1 ? y1 : (z == 2 ? y2 : y3));
+  }
+
+  // tiled right-looking block L D L^T of H
   __device__ __forceinline__ void factor() {
-    notpd = false;
+    bool bad = false;
     static_for<0, T>([&](auto kk) {
       constexpr int K = decltype(kk)::value;
-      // 4x4 diagonal factor, computed redundantly on every lane of the block
-      xch[z * 4 + x] = H[id(K, K)];
-      lds_sync();
-      double m[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) m[q] = xch[q];
-      bool bad = false;
-      double l[4][4], w[4][4], r[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) l[i][j] = 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double d = m[j * 4 + j];
-#pragma unroll
-        for (int q = 0; q < j; ++q) d = fmaT(-l[j][q], l[j][q], d);
-        if (!(d > 0.0) || !fin(d)) {
-          bad = true;
-          d = 1.0;
-        }
-        // 1/sqrt(d): hardware estimate refined by two Newton steps
-        double y = __builtin_amdgcn_rsq(d);
-        y = y * fmaT(-0.5 * d, y * y, 1.5);
-        y = y * fmaT(-0.5 * d, y * y, 1.5);
-        l[j][j] = d * y;
-        r[j] = y;
-#pragma unroll
-        for (int i = j + 1; i < 4; ++i) {
-          double v = m[i * 4 + j];
-#pragma unroll
-          for (int q = 0; q < j; ++q) v = fmaT(-l[i][q], l[j][q], v);
-          l[i][j] = v * r[j];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[i][j] = 0.0;
-        w[i][i] = r[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) {
-          double v = 0.0;
-#pragma unroll
-          for (int q = j; q < i; ++q) v = fmaT(l[i][q], w[q][j], v);
-          w[i][j] = -v * r[i];
-        }
-      }
-      notpd |= bad;
-      if (x == 0 && z == 0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) xch[16 + q] = w[q / 4][q % 4];
-      }
-      lds_sync();
-      W[K] = xch[16 + z * 4 + x];
-      WT[K] = xch[16 + x * 4 + z];
-      // panel L_IK = H_IK W^T
+      const double ndinv = ninv4(H[id(K, K)], bad);
+      H[id(K, K)] = -ndinv;
+      double U[T];  // column K before scaling (rows K+1 .. T-1)
+      // panel: -L_IK = -H_IK D_K^{-1}
       static_for<K + 1, T>([&](auto ii) {
         constexpr int I = decltype(ii)::value;
-        H[id(I, K)] = mfma4(W[K], H[id(I, K)], 0.0);
+        U[I] = H[id(I, K)];
+        H[id(I, K)] = mfma4(ndinv, U[I], 0.0);
       });
-      // trailing update H_IJ -= L_IK L_JK^T
+      // trailing update H_IJ -= L_IK H_JK^T
       static_for<K + 1, T>([&](auto jj) {
         constexpr int J = decltype(jj)::value;
-        const double nl = -H[id(J, K)];
         static_for<J, T>([&](auto ii) {
           constexpr int I = decltype(ii)::value;
-          H[id(I, J)] = mfma4(nl, H[id(I, K)], H[id(I, J)]);
+          H[id(I, J)] = mfma4(U[J], H[id(I, K)], H[id(I, J)]);
         });
       });
     });
+    notpd = bad;
   }
 
-  // solve L L^T X = R in place (x layout, one right-hand side per z)
+  // solve L D L^T X = R in place (x layout, one right-hand side per z)
   __device__ __forceinline__ void solve(double (&xr)[T]) const {
+    // L y = r
     static_for<0, T>([&](auto jj) {
       constexpr int J = decltype(jj)::value;
-      const double y = mfma4(W[J], xr[J], 0.0);
-      xr[J] = y;
-      const double ny = -y;
       static_for<J + 1, T>([&](auto ii) {
         constexpr int I = decltype(ii)::value;
-        xr[I] = mfma4(H[id(I, J)], ny, xr[I]);
+        xr[I] = mfma4(H[id(I, J)], xr[J], xr[I]);
       });
     });
-    const int src = 16 * z + 4 * blk + x;  // transpose partner (x,z) <-> (z,x)
+    // D^{-1} y
+    static_for<0, T>([&](auto jj) {
+      constexpr int J = decltype(jj)::value;
+      xr[J] = mfma4(H[id(J, J)], xr[J], 0.0);
+    });
+    // L^T x = D^{-1} y; the transposed tile comes from lane (z, x)
+    const int src = 16 * z + 4 * blk + x;
     static_for<0, T>([&](auto kk) {
       constexpr int I = T - 1 - decltype(kk)::value;
-      const double xv = mfma4(WT[I], xr[I], 0.0);
-      xr[I] = xv;
-      const double nx = -xv;
       static_for<0, I>([&](auto jj) {
         constexpr int J = decltype(jj)::value;
         const double lt = __shfl(H[id(I, J)], src);
-        xr[J] = mfma4(lt, nx, xr[J]);
+        xr[J] = mfma4(lt, xr[I], xr[J]);
       });
     });
   }
@@ -253,7 +241,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   constexpr int NP = TL::NP;
   constexpr int C = TL::C;
   __shared__ double sG[NP * NP];
-  __shared__ double sx[16 * 32];
+  __shared__ double sx[16 * 18];
   const double* Gsrc = static_cast<const double*>(prm.Gh);
   for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) sG[i] = Gsrc[i];
   __syncthreads();
@@ -270,7 +258,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   tl.z = z;
   tl.blk = blk;
   tl.sG = sG;
-  tl.xch = sx + pib * 32;
+  tl.xch = sx + pib * 18;
 
   bool vm[C];
   static_for<0, C>([&](auto mm) { vm[mm] = (16 * mm + 4 * z + x) < n; });
@@ -321,6 +309,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     });
   }
   const double tol_mu = prm.tol_mu, tol_d = prm.tol_d, tol_p = prm.tol_p, eta = prm.eta, tau = prm.tau;
+  const double inv_n = 1.0 / n;
   constexpr double BIG = 1e30;
 
   enum { kIpm = 0, kPol = 1, kDone = 2 };
@@ -352,7 +341,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
         rdm = fmax(rdm, fabs(rd[m]));
       });
       rp = bsum(sa) - 1.0;
-      mu = bsum(sal) / n;
+      mu = bsum(sal) * inv_n;
       rdm = bmax(rdm);
       bool conv;
       if constexpr (MODE == kStage1)
@@ -412,10 +401,12 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     if (__builtin_amdgcn_ballot_w64(phase != kDone) == 0) break;
 
     // ---- Newton (or finishing-step) matrix and its factorisation ----------
+    double ia[C];  // 1 / a
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
+      ia[m] = rcpT(a[m]);
       const double dp = ((freem >> m) & 1u) ? 0.0 : BIG;
-      const double di = (phase == kPol) ? dp : ((phase == kIpm) ? lam[m] / a[m] : 1.0);
+      const double di = (phase == kPol) ? dp : ((phase == kIpm) ? lam[m] * ia[m] : 1.0);
       D[m] = vm[m] ? di : 0.0;
     });
     tl.to_x(D, xl);
@@ -449,9 +440,10 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     });
     su = bsum(su);
     sw = bsum(sw);
+    const double isu = rcpT(su);
     if (phase == kPol) {
       // equality-constrained problem on the free set: a = w - nu u, 1^T a = 1
-      pnu = (sw - 1.0) / su;
+      pnu = (sw - 1.0) * isu;
       static_for<0, C>([&](auto mm) {
         pa[mm] = (vm[mm] && ((freem >> mm) & 1u)) ? fmaT(-pnu, u[mm], dx[mm]) : 0.0;
       });
@@ -462,7 +454,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     if (!two) continue;
 
     // ---- predictor step and centring --------------------------------------
-    const double dnu_aff = (sw + rp) / su;
+    const double dnu_aff = (sw + rp) * isu;
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       dx[m] = vm[m] ? fmaT(-dnu_aff, u[m], dx[m]) : 0.0;
@@ -471,8 +463,9 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     double st_aff = INFINITY;
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
-      if (vm[m] && dx[m] < 0.0) st_aff = fmin(st_aff, -a[m] / dx[m]);
-      if (vm[m] && dla[m] < 0.0) st_aff = fmin(st_aff, -lam[m] / dla[m]);
+      const double q1 = -a[m] * rcp1(dx[m]), q2 = -lam[m] * rcp1(dla[m]);
+      st_aff = (vm[m] && dx[m] < 0.0) ? fmin(st_aff, q1) : st_aff;
+      st_aff = (vm[m] && dla[m] < 0.0) ? fmin(st_aff, q2) : st_aff;
     });
     st_aff = fmin(bmin(st_aff), 1.0);
     double smu = 0.0;
@@ -480,7 +473,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       constexpr int m = decltype(mm)::value;
       if (vm[m]) smu = fmaT(a[m] + st_aff * dx[m], lam[m] + st_aff * dla[m], smu);
     });
-    const double ratio = (bsum(smu) / n) / mu;
+    const double ratio = bsum(smu) * inv_n * rcpT(mu);
     const double sig = ratio * ratio * ratio;
 
     // ---- corrector (second-order term dropped after a short affine step) ---
@@ -488,7 +481,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       const double rcv = fmaT(soc * dx[m], dla[m], a[m] * lam[m]) - sig * mu;
-      dla[m] = vm[m] ? rcv / a[m] : 0.0;  // rc / a
+      dla[m] = vm[m] ? rcv * ia[m] : 0.0;  // rc / a
       dx[m] = vm[m] ? -rd[m] - dla[m] : 0.0;
     });
     tl.to_x(dx, xl);
@@ -497,7 +490,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     double sw2 = 0.0;
     static_for<0, C>([&](auto mm) { sw2 += dx[mm]; });
     sw2 = bsum(sw2);
-    const double dnu = (sw2 + rp) / su;
+    const double dnu = (sw2 + rp) * isu;
     double dl[C];
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -507,8 +500,9 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     double step = INFINITY;
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
-      if (vm[m] && dx[m] < 0.0) step = fmin(step, -a[m] / dx[m]);
-      if (vm[m] && dl[m] < 0.0) step = fmin(step, -lam[m] / dl[m]);
+      const double q1 = -a[m] * rcp1(dx[m]), q2 = -lam[m] * rcp1(dl[m]);
+      step = (vm[m] && dx[m] < 0.0) ? fmin(step, q1) : step;
+      step = (vm[m] && dl[m] < 0.0) ? fmin(step, q2) : step;
     });
     step = bmin(step);
     const double alpha = fmin(1.0, eta * step);
