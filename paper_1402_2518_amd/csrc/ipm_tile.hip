@@ -116,8 +116,10 @@ struct Tile {
     });
   }
 
-  // xg = Gh * xa (x layout in and out)
-  __device__ __forceinline__ void gmul(const double (&xa)[T], double (&xg)[T]) const {
+  // v = Gh * xa: x layout in, compact layout out (each tile row is moved to
+  // its compact slot as soon as it is done)
+  __device__ __forceinline__ void gmul(const double (&xa)[T], double (&v)[C]) const {
+    static_for<0, C>([&](auto mm) { v[mm] = 0.0; });
     static_for<0, T>([&](auto ii) {
       constexpr int I = decltype(ii)::value;
       double acc = 0.0;
@@ -125,7 +127,8 @@ struct Tile {
         constexpr int J = decltype(jj)::value;
         acc = mfma4(sG[(4 * I + z) * NP + 4 * J + x], xa[J], acc);
       });
-      xg[I] = acc;
+      const double e = qb<0>(acc);  // element 4I + x of right-hand side 0
+      v[I / 4] = (z == I % 4) ? e : v[I / 4];
       __builtin_amdgcn_sched_barrier(0);
     });
   }
@@ -166,8 +169,12 @@ struct Tile {
     const double l32 = t32 * r2;
     const double d3 = fmaT(-l32, t32, fmaT(-l31, t31, fmaT(-l30, m30, m33)));
     const double r3 = rcpT(d3);
+    // pivots positive and finite; for a sum, s - s == 0 is a safe finiteness
+    // test (no product to contract with) and keeps the factor's register
+    // footprint lower than a class test here
     const double dmin = fmin(fmin(d0, d1), fmin(d2, d3));
-    bad |= !(dmin > 0.0) || !fin(d0 + d1 + d2 + d3);
+    const double ds = d0 + d1 + d2 + d3;
+    bad |= !(dmin > 0.0) || !(ds == ds && ds - ds == 0.0);
     // L v = -e_x, y = L^{-T} diag(r) v
     const double e0 = x == 0 ? -1.0 : 0.0, e1 = x == 1 ? -1.0 : 0.0;
     const double e2 = x == 2 ? -1.0 : 0.0, e3 = x == 3 ? -1.0 : 0.0;
@@ -188,19 +195,16 @@ struct Tile {
       constexpr int K = decltype(kk)::value;
       const double ndinv = ninv4(H[id(K, K)], bad);
       H[id(K, K)] = -ndinv;
-      double U[T];  // column K before scaling (rows K+1 .. T-1)
-      // panel: -L_IK = -H_IK D_K^{-1}
-      static_for<K + 1, T>([&](auto ii) {
-        constexpr int I = decltype(ii)::value;
-        U[I] = H[id(I, K)];
-        H[id(I, K)] = mfma4(ndinv, U[I], 0.0);
-      });
-      // trailing update H_IJ -= L_IK H_JK^T
+      // Panel -L_JK = -H_JK D_K^{-1} and trailing update H_IJ -= L_IK H_JK^T,
+      // one column J at a time from the last: column J needs -L_IK for I >= J
+      // (done) and the unscaled H_JK, so only one unscaled tile is live.
       static_for<K + 1, T>([&](auto jj) {
-        constexpr int J = decltype(jj)::value;
+        constexpr int J = T + K - decltype(jj)::value;
+        const double u = H[id(J, K)];
+        H[id(J, K)] = mfma4(ndinv, u, 0.0);
         static_for<J, T>([&](auto ii) {
           constexpr int I = decltype(ii)::value;
-          H[id(I, J)] = mfma4(U[J], H[id(I, K)], H[id(I, J)]);
+          H[id(I, J)] = mfma4(u, H[id(I, K)], H[id(I, J)]);
         });
       });
     });
@@ -321,15 +325,21 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
 
   double g[C], rd[C], D[C], dx[C], u[C], dla[C];
   double rp = 0.0, mu = 0.0;
-  double xl[T], xg[T];
+  double xl[T];
+  // gradient of the quadratic at the starting point
+  tl.to_x(a, xl);
+  tl.gmul(xl, g);
   for (;;) {
-    // ---- Gram products and phase decisions --------------------------------
-    {
-      double v[C];
-      static_for<0, C>([&](auto mm) { v[mm] = (phase == kPol) ? pa[mm] : a[mm]; });
-      tl.to_x(v, xl);
-      tl.gmul(xl, xg);
-      tl.template from_x<0>(xg, g);
+    // Gh is re-read from LDS each step rather than held in registers across
+    // iterations (it would not fit next to the factor).
+    asm volatile("" ::: "memory");
+    // ---- phase decisions ---------------------------------------------------
+    // g = Gh a is carried from step to step (see the update below); the
+    // finishing step's candidate gets its own product.
+    double gp[C];
+    if (__builtin_amdgcn_ballot_w64(phase == kPol && cand) != 0) {
+      tl.to_x(pa, xl);
+      tl.gmul(xl, gp);
     }
     if (phase == kIpm) {
       double sa = 0.0, sal = 0.0, rdm = 0.0;
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       static_for<0, C>([&](auto mm) {
         constexpr int m = decltype(mm)::value;
         const bool fr = (freem >> m) & 1u;
-        pl[m] = (vm[m] && !fr) ? g[m] - bh[m] + pnu : 0.0;
+        pl[m] = (vm[m] && !fr) ? gp[m] - bh[m] + pnu : 0.0;
         if (vm[m] && fr) wa = fmin(wa, pa[m]);
         if (vm[m] && !fr) wl = fmin(wl, pl[m]);
       });
@@ -507,9 +517,14 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     step = bmin(step);
     const double alpha = fmin(1.0, eta * step);
     if (phase == kIpm && fin(alpha)) {
+      // the Newton equations give Gh da = -r_d + dlambda - dnu 1 exactly, so
+      // the gradient follows the step without another product with Gh
       static_for<0, C>([&](auto mm) {
-        a[mm] = fmaT(alpha, dx[mm], a[mm]);
-        lam[mm] = fmaT(alpha, dl[mm], lam[mm]);
+        constexpr int m = decltype(mm)::value;
+        const double rdm = g[m] - bh[m] - lam[m] + nu;  // r_d before the step
+        g[m] = vm[m] ? fmaT(alpha, dl[m] - rdm - dnu, g[m]) : 0.0;
+        a[m] = fmaT(alpha, dx[m], a[m]);
+        lam[m] = fmaT(alpha, dl[m], lam[m]);
       });
       nu = fmaT(alpha, dnu, nu);
     }
@@ -547,8 +562,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   }
   if (prm.objective) {
     tl.to_x(a, xl);
-    tl.gmul(xl, xg);
-    tl.template from_x<0>(xg, g);
+    tl.gmul(xl, g);
     double ba = 0.0, aga = 0.0;
     static_for<0, C>([&](auto mm) {
       ba = fmaT(bh[mm], a[mm], ba);
