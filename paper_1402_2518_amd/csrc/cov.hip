@@ -7,128 +7,392 @@
 //   Cov_II = (s_p^2 / gamma) * [K^{-1}]_II,   K = [[Gh_II + diag(d_I), 1], [1^T, 0]],
 // and zero outside I; the upper-left block of K^{-1} equals
 // H^{-1} - u u^T / 1^T u with H = Gh_II + diag(d_I), u = H^{-1} 1.
-// K is inverted in LDS by the symmetric sweep operator (pivots in order, the
-// border last; the sweep keeps the matrix symmetric, so the pivot column
-// doubles as the pivot row).  One wavefront per pixel, four per workgroup;
-// the output block of each pixel is written with consecutive lanes on
-// consecutive addresses.
+// K is inverted by the symmetric sweep operator (pivots in order, the border
+// last; the sweep keeps the matrix symmetric, so the pivot column doubles as
+// the pivot row); afterwards the matrix holds -K^{-1}.
+//
+// Three paths by the size q = |I| + 1 of K.  cov_small_kernel (q <= 16) and
+// cov_mid_kernel (16 < q <= 32) put 16 lanes (one DPP row) on a pixel, four
+// pixels per wavefront; lane t keeps rows t (and t + 16) of K in registers,
+// and each pivot row reaches the other lanes by DPP row broadcasts, so the
+// sweep has no memory traffic.  Pivots and columns stop at the largest border
+// in the wavefront.  The output is written one row of the pixel's block at a
+// time with consecutive lanes on consecutive addresses; by symmetry an entry
+// (r, c) is read from the lane that owns row c.  cov_small_kernel sees every
+// pixel and flags the larger ones, cov_mid_kernel packs the flagged pixels
+// four to a wavefront, and cov_big_kernel sweeps what is left (q > 32) one
+// wavefront per pixel with K in LDS.  Noisy mixtures of a few spectra have
+// free sets of about 5 to 20 coefficients.
 #include "common.h"
 #include "kernels.h"
 
 namespace lm {
 
-__global__ __launch_bounds__(256) void cov_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
-                                                  const double* __restrict__ dcov,
-                                                  const float* __restrict__ sigma, double gamma,
-                                                  const uint8_t* __restrict__ status, int layout,
-                                                  double* __restrict__ out) {
+namespace {
+
+// number of set bits of (lo, hi) strictly below position i (0 <= i < 128)
+__device__ __forceinline__ int rank128(uint64_t lo, uint64_t hi, int i) {
+  if (i < 64) return __builtin_popcountll(lo & ((1ull << i) - 1ull));
+  return __builtin_popcountll(lo) + __builtin_popcountll(hi & ((1ull << (i - 64)) - 1ull));
+}
+__device__ __forceinline__ bool bit128(uint64_t lo, uint64_t hi, int i) {
+  return i < 64 ? ((lo >> i) & 1ull) != 0 : ((hi >> (i - 64)) & 1ull) != 0;
+}
+
+// value of lane K of this lane's 16-lane row
+template <int K>
+__device__ __forceinline__ double rowbcast(double v) {
+  return dpp<0x150 + K>(v);
+}
+
+}  // namespace
+
+// Covariance of pixel p on the calling 16-lane row (live = the row has a
+// pixel).  Every lane of the wavefront must call it together (ballots); the
+// rows' pixels are independent.  Writes big[p] = 0 when |I| + 1 <= Q (done),
+// 1 otherwise (left for a larger path).  dv, idx: this row's LDS scratch of
+// Q entries each.
+template <int Q>
+__device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const double* __restrict__ Gh, int ldg,
+                                          const double* __restrict__ dcov, const float* __restrict__ sigma,
+                                          double gamma, const uint8_t* __restrict__ status, int layout,
+                                          double* __restrict__ out, uint8_t* __restrict__ big, double* dv,
+                                          int* idx) {
+  static_assert(Q == 16 || Q == 32, "one or two rows of K per lane");
+  constexpr int H = Q / 16;           // rows of K per lane: t and t + 16
+  const int lane = threadIdx.x & 63;
+  const int t = lane & 15;            // lane within the pixel's row
+  const int gb = lane & 48;           // first lane of the row in the wavefront
+  const int ns = (n + 15) >> 4;  // 16-column slots of a row of the output
+
+  // included set: bit i of (mlo, mhi), the same on the 16 lanes of a pixel
+  uint64_t mlo = 0, mhi = 0;
+  for (int s = 0; s < ns; ++s) {
+    const int i = 16 * s + t;
+    const double d = (live && i < n) ? dcov[p * n + i] : 0.0;
+    const bool inc = live && i < n && isfin(d);
+    const uint64_t bits = (__builtin_amdgcn_ballot_w64(inc) >> gb) & 0xFFFFull;
+    if (s < 4) mlo |= bits << (16 * s);
+    else mhi |= bits << (16 * (s - 4));
+    if (inc) {
+      const int r = rank128(mlo, mhi, i);
+      if (r < Q) {
+        idx[r] = i;
+        dv[r] = d;
+      }
+    }
+  }
+  const int m = __builtin_popcountll(mlo) + __builtin_popcountll(mhi);
+  const bool small = live && m + 1 <= Q;
+  if (live && t == 0) big[p] = small ? 0 : 1;
+  lds_sync();
+
+  // rows t + 16 h of K; padding beyond the border is the identity
+  double R[H][Q];
+  static_for<0, H>([&](auto hh) {
+    constexpr int h = decltype(hh)::value;
+    const int row = t + 16 * h;
+    const int ir = (small && row < m) ? idx[row] : 0;
+    static_for<0, Q>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      double v;
+      if (!small) v = (row == c) ? 1.0 : 0.0;
+      else if (row < m && c < m) v = Gh[(int64_t)ir * ldg + idx[c]] + (row == c ? dv[row] : 0.0);
+      else if (row <= m && c <= m) v = (row == c) ? 0.0 : 1.0;
+      else v = (row == c) ? 1.0 : 0.0;
+      R[h][c] = v;
+    });
+  });
+
+  // sweep pivots 0 .. border of every pixel of the wavefront (a pivot past a
+  // pixel's border meets an identity row and leaves its border block alone);
+  // columns past the largest border are untouched identity and are skipped
+  int mmax = small ? m : 0;
+  mmax = max(mmax, __shfl_xor(mmax, 16));
+  mmax = max(mmax, __shfl_xor(mmax, 32));
+  bool singular = false;
+  static_for<0, Q>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    constexpr int kh = k / 16, kt = k % 16;
+    if (k <= mmax) {
+      const double akk = rowbcast<kt>(R[kh][k]);
+      if (!(akk != 0.0) || akk != akk) singular = true;
+      const double r = 1.0 / akk;
+      double f[H];
+      static_for<0, H>([&](auto hh) {
+        constexpr int h = decltype(hh)::value;
+        f[h] = R[h][k] * r;
+      });
+      static_for<0, Q>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        if (j <= mmax) {
+          const double b = (j == k) ? akk : rowbcast<kt>(R[kh][j]);  // K_kj before the step
+          static_for<0, H>([&](auto hh) {
+            constexpr int h = decltype(hh)::value;
+            const bool prow = (t + 16 * h == k);
+            double v;
+            if (j == k) v = prow ? -r : f[h];
+            else v = prow ? b * r : R[h][j] - f[h] * b;
+            R[h][j] = v;
+          });
+        }
+      });
+    }
+  });
+  if (!small) return;
+
+  // output; entry (r, c) of -K^{-1} is R[c / 16][r] on lane c % 16 (symmetry)
+  bool bad = status && (status[p] & (kPxNonfinite | kPxBadSigma));
+  const double s = sigma ? (double)sigma[p] : 1.0;
+  if (!(s > 0.0) || !isfin(s)) bad = true;
+  const bool nanout = bad || singular;
+  const double qnan = __builtin_nan("");
+  const double scale = -s * s / gamma;
+  const int64_t per = layout == 1 ? (int64_t)n * n : (layout == 2 ? (int64_t)n * (n + 1) / 2 : n);
+  double* o = out + p * per;
+  constexpr int NS = (128 + 15) / 16;  // column slots of the widest library
+  int rj[NS];
+  bool inj[NS];
+  static_for<0, NS>([&](auto ss) {
+    constexpr int sl = decltype(ss)::value;
+    const int j = 16 * sl + t;
+    inj[sl] = j < n && bit128(mlo, mhi, j);
+    rj[sl] = inj[sl] ? rank128(mlo, mhi, j) : 0;
+  });
+  if (layout == 3) {
+    // diagonal: entry (r, r) sits on lane r % 16; broadcast it and let the
+    // column with position r keep it
+    double dgv[NS];
+    static_for<0, NS>([&](auto ss) { dgv[decltype(ss)::value] = 0.0; });
+    static_for<0, Q - 1>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      if (r < m) {
+        const double kd = rowbcast<r % 16>(R[r / 16][r]);
+        static_for<0, NS>([&](auto ss) {
+          constexpr int sl = decltype(ss)::value;
+          dgv[sl] = (inj[sl] && rj[sl] == r) ? kd : dgv[sl];
+        });
+      }
+    });
+    static_for<0, NS>([&](auto ss) {
+      constexpr int sl = decltype(ss)::value;
+      const int j = 16 * sl + t;
+      if (j < n) o[j] = nanout ? qnan : (inj[sl] ? scale * dgv[sl] : 0.0);
+    });
+    return;
+  }
+  const bool full = layout == 1;
+  // rows outside I are zero
+  for (int i = 0; i < n; ++i) {
+    if (bit128(mlo, mhi, i)) continue;
+    const int64_t row = full ? (int64_t)i * n : (int64_t)i * (i + 1) / 2;
+    const int len = full ? n : i + 1;
+    for (int sl = 0; 16 * sl < len; ++sl) {
+      const int j = 16 * sl + t;
+      if (j < len) o[row + j] = nanout ? qnan : 0.0;
+    }
+  }
+  // rows in I, by position r (compile-time, so R[.][r] is a register)
+  static_for<0, Q - 1>([&](auto rr) {
+    constexpr int r = decltype(rr)::value;
+    if (r < m) {
+      const int i = idx[r];
+      const int64_t row = full ? (int64_t)i * n : (int64_t)i * (i + 1) / 2;
+      const int len = full ? n : i + 1;
+      static_for<0, NS>([&](auto ss) {
+        constexpr int sl = decltype(ss)::value;
+        if (16 * sl < len) {
+          const int j = 16 * sl + t;
+          double v = __shfl(R[0][r], gb + (rj[sl] & 15));
+          if constexpr (H == 2) {
+            const double v1 = __shfl(R[1][r], gb + (rj[sl] & 15));
+            v = rj[sl] >= 16 ? v1 : v;
+          }
+          if (j < len) o[row + j] = nanout ? qnan : (inj[sl] ? scale * v : 0.0);
+        }
+      });
+    }
+  });
+}
+
+// every pixel; those with |I| + 1 > 16 are flagged for the next paths
+__global__ __launch_bounds__(256) void cov_small_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
+                                                        const double* __restrict__ dcov,
+                                                        const float* __restrict__ sigma, double gamma,
+                                                        const uint8_t* __restrict__ status, int layout,
+                                                        double* __restrict__ out, uint8_t* __restrict__ big) {
+  __shared__ double dvs[16][16];
+  __shared__ int idxs[16][16];
+  const int g = threadIdx.x >> 4;
+  const int64_t p = (int64_t)blockIdx.x * 16 + g;
+  cov_group<16>(n, p, p < P, Gh, ldg, dcov, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
+}
+
+// flagged pixels only, four per wavefront: each wavefront takes 64 flags at a
+// time and hands the set ones to its rows in order
+__global__ __launch_bounds__(256, 2) void cov_mid_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
+                                                      const double* __restrict__ dcov,
+                                                      const float* __restrict__ sigma, double gamma,
+                                                      const uint8_t* __restrict__ status, int layout,
+                                                      double* __restrict__ out, uint8_t* __restrict__ big) {
+  __shared__ double dvs[16][32];
+  __shared__ int idxs[16][32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = threadIdx.x >> 4, gi = (lane >> 4) & 3;
+  const int wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  for (int64_t base = ((int64_t)blockIdx.x * wpb + wave) * 64; base < P; base += nw * 64) {
+    const bool flagged = base + lane < P && big[base + lane] != 0;
+    uint64_t todo = __builtin_amdgcn_ballot_w64(flagged);
+    while (todo) {
+      uint64_t rest = todo;
+      for (int k = 0; k < gi; ++k) rest &= rest - 1ull;
+      const bool has = rest != 0ull;
+      const int64_t p = base + (has ? __builtin_ctzll(rest) : 0);
+      cov_group<32>(n, p, has, Gh, ldg, dcov, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
+      for (int k = 0; k < 4; ++k) todo &= todo - 1ull;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
+                                                      const double* __restrict__ dcov,
+                                                      const float* __restrict__ sigma, double gamma,
+                                                      const uint8_t* __restrict__ status, int layout,
+                                                      double* __restrict__ out, const uint8_t* __restrict__ big) {
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q_max = n + 1;
-  const int stride = q_max * q_max + q_max + q_max;  // doubles per wave (ints packed after)
-  double* A = smem + wave * stride;                  // q x q, column-major
-  double* colk = A + q_max * q_max;                  // pivot column before the step
-  int* pos = (int*)(colk + q_max);                   // n: position of i in I, or -1
-  int* idx = pos + n;                                // positions -> index
+  double* A = smem + wave * (q_max * q_max + 4 * q_max);  // q x q, column-major (ld = q)
+  double* colk = A + q_max * q_max;                      // pivot column before the step
+  double* dv = colk + q_max;                             // d of the included indices, by position
+  int* idx = (int*)(dv + q_max);                         // included index at each position
   const double qnan = __builtin_nan("");
   const int64_t per = layout == 1 ? (int64_t)n * n : (layout == 2 ? (int64_t)n * (n + 1) / 2 : n);
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int j0 = lane, j1 = lane + 64;  // the output columns of this lane
 
   const int wpb = blockDim.x >> 6;
-  for (int64_t p = (int64_t)blockIdx.x * wpb + wave; p < P; p += (int64_t)gridDim.x * wpb) {
-    const double* d = dcov + p * n;
-    double* o = out + p * per;
-    bool bad = status && (status[p] & (kPxNonfinite | kPxBadSigma));
-    const double s = sigma ? (double)sigma[p] : 1.0;
-    if (!(s > 0.0) || !isfin(s)) bad = true;
-    // included set by ballot compaction
-    int m = 0;
-    for (int base = 0; base < n; base += 64) {
-      const int i = base + lane;
-      const double di = i < n ? d[i] : 0.0;
-      const bool inc = i < n && isfin(di);
-      const uint64_t mask = __builtin_amdgcn_ballot_w64(inc);
-      const int at = m + __builtin_popcountll(mask & below);
-      if (i < n) pos[i] = inc ? at : -1;
-      if (inc) idx[at] = i;
-      m += __builtin_popcountll(mask);
-    }
-    const int q = m + 1;
-    lds_sync();
-    for (int e = lane; e < q * q; e += 64) {
-      const int i = e % q, j = e / q;
-      double v;
-      if (i < m && j < m) {
-        v = Gh[(int64_t)idx[i] * ldg + idx[j]];
-        if (i == j) v += d[idx[i]];
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  for (int64_t base = ((int64_t)blockIdx.x * wpb + wave) * 64; base < P; base += nw * 64) {
+    const bool flagged = base + lane < P && big[base + lane];
+    uint64_t todo = __builtin_amdgcn_ballot_w64(flagged);
+    while (todo) {
+      const int64_t p = base + __builtin_ctzll(todo);
+      todo &= todo - 1ull;
+      const double d0 = j0 < n ? dcov[p * n + j0] : 0.0;
+      const double d1 = j1 < n ? dcov[p * n + j1] : 0.0;
+      double* o = out + p * per;
+      bool bad = status && (status[p] & (kPxNonfinite | kPxBadSigma));
+      const double s = sigma ? (double)sigma[p] : 1.0;
+      if (!(s > 0.0) || !isfin(s)) bad = true;
+      const bool in0 = j0 < n && isfin(d0), in1 = j1 < n && isfin(d1);
+      const uint64_t lo = __builtin_amdgcn_ballot_w64(in0), hi = __builtin_amdgcn_ballot_w64(in1);
+      const int m = __builtin_popcountll(lo) + __builtin_popcountll(hi);
+      const int q = m + 1;
+      const int r0 = rank128(lo, hi, j0), r1 = rank128(lo, hi, j1);
+      if (in0) {
+        idx[r0] = j0;
+        dv[r0] = d0;
+      }
+      if (in1) {
+        idx[r1] = j1;
+        dv[r1] = d1;
+      }
+      lds_sync();
+      // K into LDS; element e = a + q b walks by 64 with an incremental (a, b)
+      const int qq = q * q, da = 64 % q, db = 64 / q;
+      const int a0 = lane % q, b0 = lane / q;
+      {
+        int a = a0, b = b0;
+        for (int e = lane; e < qq; e += 64) {
+          double v;
+          if (a < m && b < m) {
+            v = Gh[(int64_t)idx[a] * ldg + idx[b]];
+            if (a == b) v += dv[a];
+          } else {
+            v = (a == m && b == m) ? 0.0 : 1.0;
+          }
+          A[e] = v;
+          a += da;
+          b += db;
+          if (a >= q) {
+            a -= q;
+            ++b;
+          }
+        }
+      }
+      lds_sync();
+      bool singular = false;
+      for (int k = 0; k < q; ++k) {
+        for (int i = lane; i < q; i += 64) colk[i] = A[k * q + i];
+        lds_sync();
+        const double akk = colk[k];
+        if (!(akk != 0.0) || akk != akk) singular = true;
+        const double r = 1.0 / akk;
+        int a = a0, b = b0;
+        for (int e = lane; e < qq; e += 64) {
+          const double aik = colk[a], akj = colk[b];
+          double v;
+          if (a == k && b == k) v = -r;
+          else if (a == k) v = akj * r;
+          else if (b == k) v = aik * r;
+          else v = A[e] - aik * akj * r;
+          A[e] = v;
+          a += da;
+          b += db;
+          if (a >= q) {
+            a -= q;
+            ++b;
+          }
+        }
+        lds_sync();
+      }
+      const bool nanout = bad || singular;
+      const double scale = -s * s / gamma;
+      if (layout == 3) {
+        if (j0 < n) o[j0] = nanout ? qnan : (in0 ? scale * A[r0 * q + r0] : 0.0);
+        if (j1 < n) o[j1] = nanout ? qnan : (in1 ? scale * A[r1 * q + r1] : 0.0);
       } else {
-        v = (i == m && j == m) ? 0.0 : 1.0;
-      }
-      A[e] = v;
-    }
-    lds_sync();
-    // sweep every pivot: afterwards A = -K^{-1}
-    bool singular = false;
-    for (int k = 0; k < q; ++k) {
-      for (int i = lane; i < q; i += 64) colk[i] = A[k * q + i];
-      lds_sync();
-      const double akk = colk[k];
-      if (!(akk != 0.0) || akk != akk) singular = true;
-      const double r = 1.0 / akk;
-      for (int e = lane; e < q * q; e += 64) {
-        const int i = e % q, j = e / q;
-        const double aik = colk[i], akj = colk[j];
-        double v;
-        if (i == k && j == k) v = -r;
-        else if (i == k) v = akj * r;
-        else if (j == k) v = aik * r;
-        else v = A[e] - aik * akj * r;
-        A[e] = v;
+        int64_t row = 0;  // offset of row i in the pixel's block
+        for (int i = 0; i < n; ++i) {
+          const bool ini = bit128(lo, hi, i);
+          const int ri = ini ? rank128(lo, hi, i) : 0;
+          const int len = layout == 1 ? n : i + 1;
+          if (j0 < len) o[row + j0] = nanout ? qnan : ((ini && in0) ? scale * A[r0 * q + ri] : 0.0);
+          if (j1 < len) o[row + j1] = nanout ? qnan : ((ini && in1) ? scale * A[r1 * q + ri] : 0.0);
+          row += len;
+        }
       }
       lds_sync();
     }
-    const bool nanout = bad || singular;
-    const double scale = -s * s / gamma;
-    if (layout == 3) {
-      for (int i = lane; i < n; i += 64) {
-        const int pi = pos[i];
-        o[i] = nanout ? qnan : (pi < 0 ? 0.0 : scale * A[pi * q + pi]);
-      }
-    } else if (layout == 1) {
-      for (int e = lane; e < n * n; e += 64) {
-        const int i = e / n, j = e - (e / n) * n;
-        const int pi = pos[i], pj = pos[j];
-        o[e] = nanout ? qnan : ((pi < 0 || pj < 0) ? 0.0 : scale * A[pj * q + pi]);
-      }
-    } else {
-      const int tot = n * (n + 1) / 2;
-      for (int e = lane; e < tot; e += 64) {
-        int i = (int)((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (i * (i + 1) / 2 > e) --i;
-        while ((i + 1) * (i + 2) / 2 <= e) ++i;
-        const int j = e - i * (i + 1) / 2;
-        const int pi = pos[i], pj = pos[j];
-        o[e] = nanout ? qnan : ((pi < 0 || pj < 0) ? 0.0 : scale * A[pj * q + pi]);
-      }
-    }
-    lds_sync();
   }
 }
 
 int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const float* sigma,
-               double gamma, const uint8_t* status, const double* out_a, int layout, double* out,
-               hipStream_t st) {
-  (void)out_a;
+               double gamma, const uint8_t* status, int layout, double* out, uint8_t* big, hipStream_t st) {
   if (P <= 0) return 0;
+  if (n < 1 || n > 128) return -5;
+  const int64_t sblocks = (P + 15) / 16;
+  hipLaunchKernelGGL(cov_small_kernel, dim3((unsigned)sblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, sigma, gamma,
+                     status, layout, out, big);
+  if (hipGetLastError() != hipSuccess) return -3;
+  if (n + 1 <= 16) return 0;  // every pixel fit the first path
+  int64_t mblocks = (P + 4 * 64 - 1) / (4 * 64);
+  if (mblocks > 4096) mblocks = 4096;
+  hipLaunchKernelGGL(cov_mid_kernel, dim3((unsigned)mblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, sigma, gamma,
+                     status, layout, out, big);
+  if (hipGetLastError() != hipSuccess) return -3;
+  if (n + 1 <= 32) return 0;
   const int q_max = n + 1;
-  const size_t per_wave = sizeof(double) * (size_t)(q_max * q_max + 2 * q_max);
-  int wpb = (int)((160 * 1024) / per_wave);
+  const size_t per_wave = sizeof(double) * (size_t)(q_max * q_max + 4 * q_max);
+  int wpb = (int)((64 * 1024) / per_wave);  // up to 4 waves, at most 64 KB per workgroup
   if (wpb > 4) wpb = 4;
-  if (wpb < 1) return -5;
-  int64_t blocks = (P + wpb - 1) / wpb;
-  if (blocks > 32768) blocks = 32768;
-  hipLaunchKernelGGL(cov_kernel, dim3((unsigned)blocks), dim3(64 * wpb), wpb * per_wave, st, n, P, Gh, ldg, dcov,
-                     sigma, gamma, status, layout, out);
+  if (wpb < 1) wpb = 1;
+  if (per_wave * wpb > 160 * 1024) return -5;
+  int64_t blocks = (P + 64 * wpb - 1) / (64 * wpb);  // one 64-pixel chunk per wavefront
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(cov_big_kernel, dim3((unsigned)blocks), dim3(64 * wpb), wpb * per_wave, st, n, P, Gh, ldg, dcov,
+                     sigma, gamma, status, layout, out, big);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

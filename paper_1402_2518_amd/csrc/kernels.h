@@ -59,9 +59,10 @@ int launch_quadform_f64(const float* Y, int64_t P, int L, const double* Ci, int 
                         hipStream_t st);
 
 // cov.hip
+// big: P bytes of workspace (pixels routed to the one-wavefront-per-pixel path)
 int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const float* sigma,
-               double gamma, const uint8_t* status_or_null, const double* out_a, int layout,
-               double* out_cov, hipStream_t st);
+               double gamma, const uint8_t* status_or_null, int layout, double* out_cov, uint8_t* big,
+               hipStream_t st);
 
 // setup.hip
 int launch_setup(const float* S_dev, int L, int N, const double* C_dev /* L x L or NULL */,

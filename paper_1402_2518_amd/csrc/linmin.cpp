@@ -58,7 +58,7 @@ void free_lib(linmin_lib l) {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Work {
-  size_t bh, c, dcov, st_a, st_lam, st_nu, st_it, st_flag, status, total;
+  size_t bh, c, dcov, big, st_a, st_lam, st_nu, st_it, st_flag, status, total;
 };
 
 Work plan(const linmin_lib_s* lib, int64_t P, const linmin_opts& o, bool want_cov) {
@@ -73,6 +73,7 @@ Work plan(const linmin_lib_s* lib, int64_t P, const linmin_opts& o, bool want_co
   w.bh = take(sizeof(double) * p * n);
   w.c = take(sizeof(double) * p);
   w.dcov = want_cov ? take(sizeof(double) * p * n) : (size_t)-1;
+  w.big = want_cov ? take(p) : (size_t)-1;
   if (o.precision == LINMIN_MIXED) {
     w.st_a = take(sizeof(double) * p * n);
     w.st_lam = take(sizeof(double) * p * n);
@@ -309,7 +310,7 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   if (rc == LINMIN_OK) rc = mark(2);
   if (rc == LINMIN_OK && want_cov)
     rc = from_launch(lm::launch_cov(lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), sigma, lib->gamma, status,
-                                    out_coeffs, o.cov_layout, out_cov, st));
+                                    o.cov_layout, out_cov, (uint8_t*)at(w.big), st));
   if (rc == LINMIN_OK) rc = mark(3);
   if (hipFreeAsync(ws, st) != hipSuccess && rc == LINMIN_OK) rc = LINMIN_EHIP;
   return rc;

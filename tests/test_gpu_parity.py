@@ -225,3 +225,42 @@ def test_noise_free_exact_recovery(dev):
     X = (A @ S.astype(np.float64)).astype(np.float32)
     g = _gpu(S, X, np.full(40, 0.01, np.float32), dev)
     assert np.abs(g["a"] - A).max() <= 1e-9
+
+
+def _cov_rel_err(g, r, mask):
+    cg, cr = g["cov"][mask], r["cov"][mask]
+    nat = g["sigma"][mask] ** 2 / g["gamma"]
+    scale = np.maximum(np.abs(cr).reshape(len(cr), -1).max(1), nat)[:, None, None]
+    return (np.abs(cg - cr) / scale).max() if len(cg) else 0.0
+
+
+def test_covariance_large_free_sets(dev):
+    """Free sets above 15 coefficients (and uncertified pixels, whose
+    covariance spans every index) go through the one-wavefront-per-pixel
+    covariance path; the small path takes the rest of the same cube."""
+    _say("[gpu] covariance of large free sets N=40")
+    w = synth.custom_workload(40, 160, 300, seed=77, n_extra=4, k_max=30, sigma=(1e-4, 2e-4))
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    g = _gpu(S, X, s, dev, cov="full")
+    r = oracle.unmix(S, X, s)
+    ok = (g["status"] == 0) & (r["status"] == 0)
+    free = (r["a"] > 0).sum(1)
+    assert (ok & (free > 15)).sum() >= 50, (ok.sum(), np.bincount(free))
+    assert (ok & (free <= 15)).sum() >= 5
+    assert np.abs(g["a"][ok] - r["a"][ok]).max() <= 1e-6
+    assert _cov_rel_err(g, r, ok) <= 1e-6
+    # the same layouts from both paths
+    N = S.shape[0]
+    packed = _gpu(S, X, s, dev, cov="packed")["cov"]
+    diag = _gpu(S, X, s, dev, cov="diag")["cov"]
+    il = np.tril_indices(N)
+    assert np.array_equal(packed, g["cov"][:, il[0], il[1]])
+    assert np.array_equal(diag, np.diagonal(g["cov"], axis1=1, axis2=2))
+    # stopped after three iterations: every pixel uncertified, covariance from
+    # the last iterate's Gh + diag(lambda / a) over all 40 coefficients
+    g3 = _gpu(S, X, s, dev, cov="full", maxit=3)
+    r3 = oracle.unmix(S, X, s, maxit=3)
+    assert (g3["status"] == oracle.MAXIT).all() and (r3["status"] == oracle.MAXIT).all()
+    assert np.abs(g3["a"] - r3["a"]).max() <= 1e-9
+    assert _cov_rel_err(g3, r3, np.ones(len(X), bool)) <= 1e-6
