@@ -21,8 +21,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector, FLOP/s
+PEAK_FP64 = 78.6e12          # MI355X FP64, dense matrix cores and vector units alike, FLOP/s
 PEAK_HBM = 8.0e12            # bytes/s
+PROFILE = os.path.join(ROOT, "profiles", "orbital_N36_L240_kernels.md")
+IPM_KERNEL = "lm::ipm_tile_kernel<9, 0>"
+IPM_SOURCES = ("paper_1402_2518_amd/csrc/ipm_tile.hip", "paper_1402_2518_amd/csrc/common.h",
+               "paper_1402_2518_amd/csrc/kernels.h")
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the interior-point kernel from the committed
+    rocprofv3 counter summary, or None when the kernel's sources have changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in IPM_SOURCES)).hexdigest()
+    for line in text.splitlines():
+        if line.startswith("traffic " + IPM_KERNEL + " "):
+            kv = dict(t.split("=", 1) for t in line.split() if "=" in t)
+            if kv.get("src_sha256") == h:
+                return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return None
 
 
 def ipm_flops_per_iteration(n: int) -> float:
@@ -141,9 +163,9 @@ def main():
     ipm_ms = float(np.mean(st64[:, 1]))
     flops = float(it64.astype(np.float64).sum()) * ipm_flops_per_iteration(N)
     achieved = flops / (ipm_ms * 1e-3)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-            "kernel": "ipm_tile_kernel<9,full> (FP64 4x4x4 MFMA tiles)", "kernel_ms": ipm_ms,
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64, "traffic": profiled_traffic(),
+            "kernel": IPM_KERNEL + " (FP64, 4x4x4 matrix-core tiles)", "kernel_ms": ipm_ms,
             "flops_per_launch": flops, "mean_iters": float(it64.mean())}
 
     result = {
