@@ -31,7 +31,11 @@ class Opts(ctypes.Structure):
                 ("tol_mu", ctypes.c_double), ("tol_d", ctypes.c_double),
                 ("tol_p", ctypes.c_double), ("eta", ctypes.c_double),
                 ("lambda0", ctypes.c_double), ("tau", ctypes.c_double),
-                ("deg_tol", ctypes.c_double)]
+                ("deg_tol", ctypes.c_double), ("constraint", ctypes.c_int)]
+
+
+# constraint options of IPLS besides a >= 0
+STO, SLO, POS = 0, 1, 2  # sum-to-one, sum-lower-than-one, positivity only
 
 
 def build(force: bool = True, src: str = SRC, out: str = LIB) -> str:

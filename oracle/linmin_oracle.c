@@ -23,6 +23,9 @@
  *         min 1/2 a^T Gh a - bh^T a,  a >= 0, 1^T a = 1,
  *     Gh = G / gamma, bh = b / gamma, multipliers lambda (for a >= 0) and
  *     nu (for 1^T a = 1), one common step length for primal and dual.
+ *     The other constraint options of IPLS: sum-lower-than-one (1^T a <= 1,
+ *     a slack s >= 0 with multiplier nu >= 0 as one more complementarity
+ *     pair) and positivity only (no sum row, nu = 0).
  *  4. A finishing step once the barrier parameter is small: the optimal
  *     partition is read off the iterate (free where a_i > lambda_i), the
  *     equality-constrained problem on the free set is solved exactly, and
@@ -65,7 +68,14 @@ typedef struct {
     double lambda0;    /* starting multiplier value */
     double tau;        /* KKT sign tolerance of the finishing step */
     double deg_tol;    /* strict-complementarity threshold for DEGENERATE */
+    int constraint;    /* LO_STO, LO_SLO or LO_POS (the paper's IPLS options) */
 } lo_opts;
+
+/* constraints besides a >= 0 (Sec. 2.2 and the options of IPLS named in the
+ * results: sum-to-one, sum-lower-than-one, positivity only) */
+#define LO_STO 0   /* 1^T a = 1 (eq. 4) */
+#define LO_SLO 1   /* 1^T a <= 1 */
+#define LO_POS 2   /* no constraint on the sum */
 
 void lo_default_opts(lo_opts *o)
 {
@@ -78,6 +88,7 @@ void lo_default_opts(lo_opts *o)
     o->lambda0 = 0.1;
     o->tau = 1e-11;
     o->deg_tol = 1e-9;
+    o->constraint = LO_STO;
 }
 
 /* In-place Cholesky A = R R^T of an n x n row-major SPD matrix (lower part
@@ -199,41 +210,62 @@ static void work_free(work_t *W)
     free(W->fidx); free(W->aidx); free(W->isfree);
 }
 
-/* Newton direction for complementarity target rc (Sec. 16.6 of Nocedal &
- * Wright with the equality row eliminated through u = H^{-1} 1):
- *   r = -r_d - rc/a, w = H^{-1} r, dnu = (1^T w + r_p) / 1^T u,
+/* Newton direction for complementarity targets rc (pairs a_i lambda_i) and
+ * rcs (the pair s nu of the slack of 1^T a <= 1), Sec. 16.6 of Nocedal &
+ * Wright with the sum row eliminated through u = H^{-1} 1:
+ *   r = -r_d - rc/a, w = H^{-1} r,
+ *   sum-to-one:         dnu = (1^T w + r_p) / 1^T u
+ *   sum-lower-than-one: dnu = (1^T w + r_p - rcs/nu) / (1^T u + s/nu),
+ *                       ds = (-rcs - s dnu) / nu
+ *   positivity only:    dnu = 0
  *   da = w - dnu u, dl = -rc/a - D da.                                   */
-static void newton_dir(const work_t *W, int N, const double *a, const double *rd, double rp,
-                       double su, const double *rc, double *da, double *dl, double *dnu)
+static void newton_dir(const work_t *W, int N, int cons, const double *a, const double *rd,
+                       double rp, double su, const double *rc, double s, double nu, double rcs,
+                       double *da, double *dl, double *dnu, double *ds)
 {
     for (int i = 0; i < N; ++i) W->w[i] = -rd[i] - rc[i] / a[i];
     chol_solve(W->H, N, N, W->w);
     double sw = 0.0;
     for (int i = 0; i < N; ++i) sw += W->w[i];
-    *dnu = (sw + rp) / su;
+    if (cons == LO_POS) *dnu = 0.0;
+    else if (cons == LO_SLO) *dnu = (sw + rp - rcs / nu) / (su + s / nu);
+    else *dnu = (sw + rp) / su;
+    *ds = (cons == LO_SLO) ? (-rcs - s * *dnu) / nu : 0.0;
     for (int i = 0; i < N; ++i) {
         da[i] = W->w[i] - *dnu * W->u[i];
         dl[i] = -rc[i] / a[i] - W->D[i] * da[i];
     }
 }
 
+/* largest t in (0, inf] keeping the slack pair (s, nu) >= 0 */
+static double pair_step(double s, double ds, double nu, double dnu)
+{
+    double t = INFINITY;
+    if (ds < 0.0) t = fmin(t, -s / ds);
+    if (dnu < 0.0) t = fmin(t, -nu / dnu);
+    return t;
+}
+
 /* Exact solve of the equality-constrained problem on the free set F:
- * Gh_FF a_F + nu 1 = bh_F, 1^T a_F = 1, a_A = 0, lambda_F = 0,
- * lambda_A = Gh_AF a_F - bh_A + nu.  Leaves the Cholesky factor of Gh_FF in
- * W->H (ld = N) and u_F = Gh_FF^{-1} 1 in W->u.  Returns 0 or -1 (Gh_FF not PD). */
+ * Gh_FF a_F + nu 1 = bh_F, 1^T a_F = 1 (bordered; otherwise nu = 0 and no
+ * sum row), a_A = 0, lambda_F = 0, lambda_A = Gh_AF a_F - bh_A + nu.
+ * Leaves the Cholesky factor of Gh_FF in W->H (ld = N) and u_F = Gh_FF^{-1} 1
+ * in W->u.  Returns 0 or -1 (Gh_FF not PD). */
 static int free_set_solve(work_t *W, const double *Gh, const double *bh, int N, int nF,
-                          double *a, double *lam, double *nu)
+                          int bordered, double *a, double *lam, double *nu)
 {
     const int *F = W->fidx;
     for (int p = 0; p < nF; ++p)
         for (int q = 0; q <= p; ++q) W->H[p * N + q] = Gh[F[p] * N + F[q]];
-    if (chol(W->H, nF, N) != 0) return -1;
+    if (nF > 0 && chol(W->H, nF, N) != 0) return -1;
     double su = 0.0, sw = 0.0;
     for (int p = 0; p < nF; ++p) { W->u[p] = 1.0; W->w[p] = bh[F[p]]; }
     chol_solve(W->H, nF, N, W->u);
     chol_solve(W->H, nF, N, W->w);
     for (int p = 0; p < nF; ++p) { su += W->u[p]; sw += W->w[p]; }
-    *nu = (sw - 1.0) / su;
+    /* with the sum row: 1^T a_F = 1; without it (positivity only, or a slack
+     * of 1^T a <= 1 that is not at its bound) the multiplier is zero */
+    *nu = bordered ? (sw - 1.0) / su : 0.0;
     for (int i = 0; i < N; ++i) a[i] = 0.0;
     for (int p = 0; p < nF; ++p) a[F[p]] = W->w[p] - *nu * W->u[p];
     for (int i = 0; i < N; ++i) {
@@ -282,22 +314,28 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
         if (fabs(bh[i]) > bmax) bmax = fabs(bh[i]);
     }
 
-    /* interior-point iterations */
-    double nu = 0.0;
-    for (int i = 0; i < N; ++i) { a[i] = 1.0 / N; lam[i] = o->lambda0; }
+    /* interior-point iterations; with sum-lower-than-one the slack s of
+     * 1^T a <= 1 and its multiplier nu form one more complementarity pair */
+    const int cons = o->constraint, slo = cons == LO_SLO, pos = cons == LO_POS;
+    const int npair = N + slo;
+    double nu = 0.0, s = 0.0;
+    const double a0 = 1.0 / npair;
+    for (int i = 0; i < N; ++i) { a[i] = a0; lam[i] = o->lambda0; }
+    if (slo) { s = a0; nu = o->lambda0; }
     int converged = 0, it = 0, notpd = 0;
     double *rd = W->r;
     for (;; ++it) {
-        double rp = -1.0, mu = 0.0, rdmax = 0.0;
+        double rp = slo ? s - 1.0 : -1.0, mu = slo ? s * nu : 0.0, rdmax = 0.0;
         for (int i = 0; i < N; ++i) {
-            double s = -bh[i] - lam[i] + nu;
-            for (int j = 0; j < N; ++j) s += Gh[i * N + j] * a[j];
-            rd[i] = s;
-            if (fabs(s) > rdmax) rdmax = fabs(s);
+            double v = -bh[i] - lam[i] + nu;
+            for (int j = 0; j < N; ++j) v += Gh[i * N + j] * a[j];
+            rd[i] = v;
+            if (fabs(v) > rdmax) rdmax = fabs(v);
             rp += a[i];
             mu += a[i] * lam[i];
         }
-        mu /= N;
+        if (pos) rp = 0.0;
+        mu /= npair;
         if (mu <= o->tol_mu && rdmax <= o->tol_d * (1.0 + bmax) && fabs(rp) <= o->tol_p) {
             converged = 1;
             break;
@@ -314,15 +352,17 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
         for (int i = 0; i < N; ++i) su += W->u[i];
 
         /* predictor (affine scaling) */
-        double dnu_aff, dnu;
+        double dnu_aff, dnu, ds_aff, ds;
         for (int i = 0; i < N; ++i) W->rc[i] = a[i] * lam[i];
-        newton_dir(W, N, a, rd, rp, su, W->rc, W->da_aff, W->dl_aff, &dnu_aff);
+        newton_dir(W, N, cons, a, rd, rp, su, W->rc, s, nu, s * nu, W->da_aff, W->dl_aff, &dnu_aff,
+                   &ds_aff);
         double t_aff = fmin(max_step(a, W->da_aff, N), max_step(lam, W->dl_aff, N));
+        if (slo) t_aff = fmin(t_aff, pair_step(s, ds_aff, nu, dnu_aff));
         if (t_aff > 1.0) t_aff = 1.0;
-        double mu_aff = 0.0;
+        double mu_aff = slo ? (s + t_aff * ds_aff) * (nu + t_aff * dnu_aff) : 0.0;
         for (int i = 0; i < N; ++i)
             mu_aff += (a[i] + t_aff * W->da_aff[i]) * (lam[i] + t_aff * W->dl_aff[i]);
-        mu_aff /= N;
+        mu_aff /= npair;
         double ratio = mu_aff / mu;
         double sigma = ratio * ratio * ratio;
 
@@ -332,8 +372,10 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
         const double soc = t_aff >= 0.1 ? 1.0 : 0.0;
         for (int i = 0; i < N; ++i)
             W->rc[i] = a[i] * lam[i] + soc * W->da_aff[i] * W->dl_aff[i] - sigma * mu;
-        newton_dir(W, N, a, rd, rp, su, W->rc, W->da, W->dl, &dnu);
+        const double rcs = s * nu + soc * ds_aff * dnu_aff - sigma * mu;
+        newton_dir(W, N, cons, a, rd, rp, su, W->rc, s, nu, rcs, W->da, W->dl, &dnu, &ds);
         double t = fmin(max_step(a, W->da, N), max_step(lam, W->dl, N));
+        if (slo) t = fmin(t, pair_step(s, ds, nu, dnu));
         double alpha = o->eta * t;
         if (alpha > 1.0) alpha = 1.0;
         for (int i = 0; i < N; ++i) {
@@ -341,44 +383,65 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
             lam[i] += alpha * W->dl[i];
         }
         nu += alpha * dnu;
+        s += alpha * ds;
     }
     *iters = it;
     if (notpd) st |= LO_NOT_PD;
     else if (!converged) st |= LO_MAXIT;
 
-    /* finishing step: certify the optimal partition */
-    int certified = 0;
+    /* finishing step: certify the optimal partition.  For sum-lower-than-one
+     * the slack is one more index: free (s > 0, nu = 0: no sum row) or at its
+     * bound (s = 0: the sum row, nu >= 0). */
+    int certified = 0, slack_free = pos;
     if (converged) {
         double *ta = W->da, *tl = W->dl, tnu = 0.0;
         for (int i = 0; i < N; ++i) W->isfree[i] = a[i] > lam[i];
+        if (slo) slack_free = s > nu;
         for (int k = 0; k <= o->max_polish; ++k) {
             int nF = 0, nA = 0;
             for (int i = 0; i < N; ++i) {
                 if (W->isfree[i]) W->fidx[nF++] = i;
                 else W->aidx[nA++] = i;
             }
-            if (nF == 0) break;
-            if (free_set_solve(W, Gh, bh, N, nF, ta, tl, &tnu) != 0) break;
+            const int bordered = !slack_free;
+            if (nF == 0 && bordered) break;
+            if (free_set_solve(W, Gh, bh, N, nF, bordered, ta, tl, &tnu) != 0) break;
+            /* worst violation: a free coefficient (or free slack) below zero,
+             * or an active multiplier (or the sum multiplier) below zero */
             int worst_a = -1, worst_l = -1;
             double va = -o->tau, vl = -o->tau;
             for (int p = 0; p < nF; ++p)
                 if (ta[W->fidx[p]] < va) { va = ta[W->fidx[p]]; worst_a = W->fidx[p]; }
             for (int p = 0; p < nA; ++p)
                 if (tl[W->aidx[p]] < vl) { vl = tl[W->aidx[p]]; worst_l = W->aidx[p]; }
+            if (slo) {
+                double sum = 0.0;
+                for (int p = 0; p < nF; ++p) sum += ta[W->fidx[p]];
+                if (slack_free && 1.0 - sum < va) { va = 1.0 - sum; worst_a = N; }
+                if (!slack_free && tnu < vl) { vl = tnu; worst_l = N; }
+            }
             if (worst_a < 0 && worst_l < 0) {
                 certified = 1;
                 memcpy(a, ta, sizeof(double) * N);
                 memcpy(lam, tl, sizeof(double) * N);
                 nu = tnu;
+                if (slo) {
+                    double sum = 0.0;
+                    for (int i = 0; i < N; ++i) sum += a[i];
+                    s = slack_free ? 1.0 - sum : 0.0;
+                }
                 break;
             }
-            if (worst_a >= 0 && va <= vl) W->isfree[worst_a] = 0;
-            else W->isfree[worst_l] = 1;
+            const int flip = (worst_a >= 0 && va <= vl) ? worst_a : worst_l;
+            if (flip == N) slack_free = !slack_free;
+            else W->isfree[flip] = (flip == worst_l);
         }
         if (!certified) st |= LO_INEXACT;
-        else
+        else {
             for (int i = 0; i < N; ++i)
                 if (W->isfree[i] ? a[i] < o->deg_tol : lam[i] < o->deg_tol) st |= LO_DEGENERATE;
+            if (slo && (slack_free ? s < o->deg_tol : nu < o->deg_tol)) st |= LO_DEGENERATE;
+        }
     }
     *nu_out = nu;
 
@@ -399,6 +462,10 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
         if (st & LO_BAD_SIGMA) { fill_nan(cov, (long)N * N); return st; }
         double scale = (double)sig * sig / gam;
         int nF = 0, ok = 1;
+        /* the sum row borders K with corner -s/nu: 0 at a binding sum-to-one,
+         * none (an infinite corner) without a binding sum constraint */
+        double corner_inv = 1.0;   /* 1 / (1^T u - corner) multiplies u u^T */
+        int bordered = certified ? !slack_free : !pos;
         if (certified) {
             /* H restricted to the free set; W->H holds nothing reusable here */
             for (int i = 0; i < N; ++i) if (W->isfree[i]) W->fidx[nF++] = i;
@@ -419,12 +486,14 @@ static unsigned pixel(const double *Gh, const double *Gmat, double gam, const do
         for (int p = 0; p < nF; ++p) W->u[p] = 1.0;
         chol_solve(W->H, nF, N, W->u);
         for (int p = 0; p < nF; ++p) su += W->u[p];
+        if (bordered) corner_inv = 1.0 / (su + ((slo && !certified) ? s / nu : 0.0));
+        else corner_inv = 0.0;
         for (int q = 0; q < nF; ++q) {
             for (int p = 0; p < nF; ++p) W->tmp[p] = (p == q);
             chol_solve(W->H, nF, N, W->tmp);  /* column q of H^{-1} */
             for (int p = 0; p < nF; ++p)
                 cov[(long)W->fidx[p] * N + W->fidx[q]] =
-                    scale * (W->tmp[p] - W->u[p] * W->u[q] / su);
+                    scale * (W->tmp[p] - W->u[p] * W->u[q] * corner_inv);
         }
     }
     return st;

@@ -169,3 +169,55 @@ def disjoint_library(N: int, L: int, rng, equal: bool = False) -> np.ndarray:
         vals = base if equal else rng.integers(1, 64, size=width) / 64.0
         S[i, i * width:(i + 1) * width] = vals
     return S
+
+
+# ----------------------------------------------------- other constraint sets
+# The IPLS options besides sum-to-one: sum-lower-than-one (a >= 0,
+# 1^T a <= 1) and positivity only (a >= 0).
+
+def solid_simplex_project(V: np.ndarray) -> np.ndarray:
+    """Euclidean projection of each row onto {a >= 0, 1^T a <= 1}: the
+    positive part when its sum is at most one, else the projection onto the
+    simplex (the sum constraint is then active)."""
+    V = np.atleast_2d(np.asarray(V, np.float64))
+    Pp = np.maximum(V, 0.0)
+    over = Pp.sum(axis=1) > 1.0
+    out = Pp.copy()
+    if over.any():
+        out[over] = simplex_project(V[over])
+    return out
+
+
+def natural_residual_set(G: np.ndarray, B: np.ndarray, A: np.ndarray, constraint: str) -> np.ndarray:
+    """Natural residual ``||a - P(a - grad)||_inf`` for the constraint set
+    ``"pos"`` (projection = positive part) or ``"slo"`` (solid simplex)."""
+    gam = np.max(np.diag(G))
+    V = A - (A @ (G / gam) - B / gam)
+    Pj = np.maximum(V, 0.0) if constraint == "pos" else solid_simplex_project(V)
+    return np.abs(A - Pj).max(axis=1)
+
+
+def brute_force_pos(G: np.ndarray, B: np.ndarray, tol: float = 1e-12) -> np.ndarray:
+    """Exact positivity-only minimiser per row by enumerating the free set S:
+    ``G_SS a_S = b_S`` (the empty set gives a = 0); keep feasible solutions
+    and return the one with the smallest criterion."""
+    G = np.asarray(G, np.float64)
+    B = np.atleast_2d(np.asarray(B, np.float64))
+    P, N = B.shape
+    best = np.zeros(P)  # a = 0
+    A = np.zeros((P, N))
+    for r in range(1, N + 1):
+        for sub in itertools.combinations(range(N), r):
+            s = list(sub)
+            Gs = G[np.ix_(s, s)]
+            if abs(np.linalg.det(Gs)) < 1e-300:
+                continue
+            sol = np.linalg.solve(Gs, B[:, s].T)
+            a = np.zeros((P, N))
+            a[:, s] = sol.T
+            feas = (sol >= -tol).all(axis=0)
+            f = objective(G, B, a)
+            take = feas & (f < best - 1e-15 * np.abs(f).clip(1))
+            best[take] = f[take]
+            A[take] = a[take]
+    return A

@@ -14,19 +14,27 @@ import pins
 from paper_1402_2518_amd import synth
 
 MUTANTS = {
-    "dual residual drops nu": ("double s = -bh[i] - lam[i] + nu;", "double s = -bh[i] - lam[i];"),
+    "dual residual drops nu": ("double v = -bh[i] - lam[i] + nu;", "double v = -bh[i] - lam[i];"),
     "wrong sign of r_p in dnu": ("*dnu = (sw + rp) / su;", "*dnu = (sw - rp) / su;"),
     "dl drops the D da term": ("dl[i] = -rc[i] / a[i] - W->D[i] * da[i];", "dl[i] = -rc[i] / a[i];"),
     "unscaled projection": ("bh[i] = s / gam;", "bh[i] = s;"),
-    "covariance without u u^T": ("scale * (W->tmp[p] - W->u[p] * W->u[q] / su);", "scale * (W->tmp[p]);"),
+    "covariance without u u^T": ("scale * (W->tmp[p] - W->u[p] * W->u[q] * corner_inv);", "scale * (W->tmp[p]);"),
     "covariance scaled by s not s^2": ("double scale = (double)sig * sig / gam;", "double scale = (double)sig / gam;"),
     "objective drops the factor 2": ("(c - 2.0 * ba + q)", "(c - ba + q)"),
     "finishing step accepts any partition": ("if (worst_a < 0 && worst_l < 0) {", "if (1) {"),
     "renormalised pixel uses Lc transposed": ("for (int l = j; l < L; ++l) s += (double)x[l] * Lc[l * L + j];",
                                               "for (int l = j; l < L; ++l) s += (double)x[l] * Lc[j * L + l];"),
     "corrector safeguard removed": ("const double soc = t_aff >= 0.1 ? 1.0 : 0.0;", "const double soc = 1.0;"),
-    "gram transposed index": ("for (int j = 0; j < N; ++j) s += Gh[i * N + j] * a[j];",
-                              "for (int j = 0; j < N; ++j) s += Gh[i * N + j] * a[i];"),
+    "gram transposed index": ("for (int j = 0; j < N; ++j) v += Gh[i * N + j] * a[j];",
+                              "for (int j = 0; j < N; ++j) v += Gh[i * N + j] * a[i];"),
+    "slack corner dropped from dnu": ("else if (cons == LO_SLO) *dnu = (sw + rp - rcs / nu) / (su + s / nu);",
+                                      "else if (cons == LO_SLO) *dnu = (sw + rp - rcs / nu) / su;"),
+    "positivity only finishes with the sum row": ("int certified = 0, slack_free = pos;",
+                                                  "int certified = 0, slack_free = 0;"),
+    "free slack keeps the sum row": ("*nu = bordered ? (sw - 1.0) / su : 0.0;", "*nu = (sw - 1.0) / su;"),
+    "uncertified covariance drops the slack corner": (
+        "if (bordered) corner_inv = 1.0 / (su + ((slo && !certified) ? s / nu : 0.0));",
+        "if (bordered) corner_inv = 1.0 / su;"),
 }
 
 
@@ -88,6 +96,34 @@ def pin_failures(lib):
     Wh = V @ np.diag(ev ** -0.5) @ V.T
     Sw, Xw = Sc.astype(float) @ Wh, Xc.astype(float) @ Wh
     check("renormalisation", lambda: np.abs(rc["a"] - pins.brute_force(Sw @ Sw.T, Xw @ Sw.T)[0]).max() <= 1e-9)
+
+    # the other constraint options on mixtures whose sums straddle one
+    rng = np.random.default_rng(31)
+    N, L = 6, 40
+    Sk = rng.uniform(0.05, 1.0, (N, L)).astype(np.float32)
+    Ak = rng.dirichlet(np.ones(N), 60) * rng.uniform(0.6, 1.4, (60, 1))
+    Xk = (Ak @ Sk.astype(float) + 0.01 * rng.standard_normal((60, L))).astype(np.float32)
+    Gk, Bk = pins.gram(Sk), pins.proj(Sk, Xk)
+    a_pos = pins.brute_force_pos(Gk, Bk)
+    rp_ = oracle.unmix(Sk, Xk, None, cov=False, constraint=oracle.POS, lib=lib)
+    check("positivity only", lambda: np.abs(rp_["a"] - a_pos).max() <= 1e-9)
+    rs_ = oracle.unmix(Sk, Xk, None, cov=False, constraint=oracle.SLO, lib=lib)
+    want = np.where((a_pos.sum(1) <= 1.0)[:, None], a_pos, pins.brute_force(Gk, Bk)[0])
+    check("sum lower than one", lambda: np.abs(rs_["a"] - want).max() <= 1e-9)
+    r3 = oracle.unmix(Sk[:5], Xk[:10], None, constraint=oracle.SLO, maxit=3, lib=lib)
+
+    def corner_ok():
+        Gc = pins.gram(Sk[:5])
+        gam = Gc.diagonal().max()
+        for p in range(10):
+            a, lam, nu = r3["a"][p], r3["lam"][p], r3["nu"][p]
+            H = Gc / gam + np.diag(lam / a)
+            K = np.block([[H, np.ones((5, 1))], [np.ones((1, 5)), np.array([[-(1.0 - a.sum()) / nu]])]])
+            want_c = np.linalg.inv(K)[:5, :5] / gam
+            if np.abs(r3["cov"][p] - want_c).max() > 1e-9 * np.abs(want_c).max():
+                return False
+        return True
+    check("slack corner covariance", corner_ok)
     return out
 
 
