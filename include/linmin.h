@@ -72,14 +72,26 @@ typedef struct linmin_lib_s *linmin_lib;
 
 #define LINMIN_N_MAX 128 /* largest library supported */
 
+/* Constraint on the sum of the coefficients besides a >= 0 (eq. 3): the
+ * options of IPLS named in the results (Sec. 3.1 and 3.3; the OMEGA run of
+ * Sec. 4.1 uses LINMIN_SLO). */
+#define LINMIN_STO 0 /* sum-to-one, 1^T a = 1 (eq. 4) */
+#define LINMIN_SLO 1 /* sum-lower-than-one, 1^T a <= 1 */
+#define LINMIN_POS 2 /* positivity only */
+
 typedef struct {
     int precision;      /* LINMIN_FP64 or LINMIN_MIXED */
     int cov_layout;     /* LINMIN_COV_* */
     int maxit;          /* interior-point iteration cap (default 100) */
     int max_polish;     /* partition corrections in the finishing step (16) */
+    int constraint;     /* LINMIN_STO (default), LINMIN_SLO or LINMIN_POS.  With
+                           SLO the slack of 1^T a <= 1 and the sum multiplier
+                           form one more complementarity pair; the covariance
+                           has the sum row only where the constraint binds
+                           (none for POS). */
     double tol_mu;      /* stop when mu <= tol_mu (1e-13) ...          */
     double tol_d;       /* ... ||r_d||_inf <= tol_d (1 + ||bh||_inf) (1e-12) */
-    double tol_p;       /* ... and |1^T a - 1| <= tol_p (1e-13)        */
+    double tol_p;       /* ... and |1^T a (+ slack) - 1| <= tol_p (1e-13) */
     double eta;         /* fraction of the step to the boundary (0.99) */
     double lambda0;     /* starting multipliers (0.1) */
     double tau;         /* KKT sign tolerance of the finishing step (1e-11) */

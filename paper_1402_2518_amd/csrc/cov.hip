@@ -54,7 +54,8 @@ __device__ __forceinline__ double rowbcast(double v) {
 // Q entries each.
 template <int Q>
 __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const double* __restrict__ Gh, int ldg,
-                                          const double* __restrict__ dcov, const float* __restrict__ sigma,
+                                          const double* __restrict__ dcov, const double* __restrict__ corner,
+                                          const float* __restrict__ sigma,
                                           double gamma, const uint8_t* __restrict__ status, int layout,
                                           double* __restrict__ out, uint8_t* __restrict__ big, double* dv,
                                           int* idx) {
@@ -83,7 +84,11 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
     }
   }
   const int m = __builtin_popcountll(mlo) + __builtin_popcountll(mhi);
-  const bool small = live && m + 1 <= Q;
+  // sum row: present unless the corner is -inf (no sum constraint binding)
+  const double cval = live ? corner[p] : 0.0;
+  const int bord = cval == -(double)INFINITY ? 0 : 1;
+  const int q = m + bord;
+  const bool small = live && q <= Q;
   if (live && t == 0) big[p] = small ? 0 : 1;
   lds_sync();
 
@@ -98,7 +103,7 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
       double v;
       if (!small) v = (row == c) ? 1.0 : 0.0;
       else if (row < m && c < m) v = Gh[(int64_t)ir * ldg + idx[c]] + (row == c ? dv[row] : 0.0);
-      else if (row <= m && c <= m) v = (row == c) ? 0.0 : 1.0;
+      else if (bord && row <= m && c <= m) v = (row == c) ? cval : 1.0;
       else v = (row == c) ? 1.0 : 0.0;
       R[h][c] = v;
     });
@@ -107,7 +112,7 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
   // sweep pivots 0 .. border of every pixel of the wavefront (a pivot past a
   // pixel's border meets an identity row and leaves its border block alone);
   // columns past the largest border are untouched identity and are skipped
-  int mmax = small ? m : 0;
+  int mmax = small ? q - 1 : -1;
   mmax = max(mmax, __shfl_xor(mmax, 16));
   mmax = max(mmax, __shfl_xor(mmax, 32));
   bool singular = false;
@@ -164,7 +169,7 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
     // column with position r keep it
     double dgv[NS];
     static_for<0, NS>([&](auto ss) { dgv[decltype(ss)::value] = 0.0; });
-    static_for<0, Q - 1>([&](auto rr) {
+    static_for<0, Q>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
       if (r < m) {
         const double kd = rowbcast<r % 16>(R[r / 16][r]);
@@ -193,7 +198,7 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
     }
   }
   // rows in I, by position r (compile-time, so R[.][r] is a register)
-  static_for<0, Q - 1>([&](auto rr) {
+  static_for<0, Q>([&](auto rr) {
     constexpr int r = decltype(rr)::value;
     if (r < m) {
       const int i = idx[r];
@@ -218,6 +223,7 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
 // every pixel; those with |I| + 1 > 16 are flagged for the next paths
 __global__ __launch_bounds__(256) void cov_small_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
                                                         const double* __restrict__ dcov,
+                                                        const double* __restrict__ corner,
                                                         const float* __restrict__ sigma, double gamma,
                                                         const uint8_t* __restrict__ status, int layout,
                                                         double* __restrict__ out, uint8_t* __restrict__ big) {
@@ -225,13 +231,14 @@ __global__ __launch_bounds__(256) void cov_small_kernel(int n, int64_t P, const 
   __shared__ int idxs[16][16];
   const int g = threadIdx.x >> 4;
   const int64_t p = (int64_t)blockIdx.x * 16 + g;
-  cov_group<16>(n, p, p < P, Gh, ldg, dcov, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
+  cov_group<16>(n, p, p < P, Gh, ldg, dcov, corner, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
 }
 
 // flagged pixels only, four per wavefront: each wavefront takes 64 flags at a
 // time and hands the set ones to its rows in order
 __global__ __launch_bounds__(256, 2) void cov_mid_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
                                                       const double* __restrict__ dcov,
+                                                      const double* __restrict__ corner,
                                                       const float* __restrict__ sigma, double gamma,
                                                       const uint8_t* __restrict__ status, int layout,
                                                       double* __restrict__ out, uint8_t* __restrict__ big) {
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(256, 2) void cov_mid_kernel(int n, int64_t P, const
       for (int k = 0; k < gi; ++k) rest &= rest - 1ull;
       const bool has = rest != 0ull;
       const int64_t p = base + (has ? __builtin_ctzll(rest) : 0);
-      cov_group<32>(n, p, has, Gh, ldg, dcov, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
+      cov_group<32>(n, p, has, Gh, ldg, dcov, corner, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
       for (int k = 0; k < 4; ++k) todo &= todo - 1ull;
     }
   }
@@ -257,6 +264,7 @@ __global__ __launch_bounds__(256, 2) void cov_mid_kernel(int n, int64_t P, const
 
 __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
                                                       const double* __restrict__ dcov,
+                                                      const double* __restrict__ corner,
                                                       const float* __restrict__ sigma, double gamma,
                                                       const uint8_t* __restrict__ status, int layout,
                                                       double* __restrict__ out, const uint8_t* __restrict__ big) {
@@ -288,7 +296,9 @@ __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const do
       const bool in0 = j0 < n && isfin(d0), in1 = j1 < n && isfin(d1);
       const uint64_t lo = __builtin_amdgcn_ballot_w64(in0), hi = __builtin_amdgcn_ballot_w64(in1);
       const int m = __builtin_popcountll(lo) + __builtin_popcountll(hi);
-      const int q = m + 1;
+      const double cval = corner[p];
+      const int bord = cval == -(double)INFINITY ? 0 : 1;
+      const int q = m + bord;
       const int r0 = rank128(lo, hi, j0), r1 = rank128(lo, hi, j1);
       if (in0) {
         idx[r0] = j0;
@@ -310,7 +320,7 @@ __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const do
             v = Gh[(int64_t)idx[a] * ldg + idx[b]];
             if (a == b) v += dv[a];
           } else {
-            v = (a == m && b == m) ? 0.0 : 1.0;
+            v = (a == m && b == m) ? cval : 1.0;  // border row and corner
           }
           A[e] = v;
           a += da;
@@ -368,18 +378,19 @@ __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const do
   }
 }
 
-int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const float* sigma,
-               double gamma, const uint8_t* status, int layout, double* out, uint8_t* big, hipStream_t st) {
+int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const double* corner,
+               const float* sigma, double gamma, const uint8_t* status, int layout, double* out, uint8_t* big,
+               hipStream_t st) {
   if (P <= 0) return 0;
   if (n < 1 || n > 128) return -5;
   const int64_t sblocks = (P + 15) / 16;
-  hipLaunchKernelGGL(cov_small_kernel, dim3((unsigned)sblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, sigma, gamma,
+  hipLaunchKernelGGL(cov_small_kernel, dim3((unsigned)sblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, corner, sigma, gamma,
                      status, layout, out, big);
   if (hipGetLastError() != hipSuccess) return -3;
   if (n + 1 <= 16) return 0;  // every pixel fit the first path
   int64_t mblocks = (P + 4 * 64 - 1) / (4 * 64);
   if (mblocks > 4096) mblocks = 4096;
-  hipLaunchKernelGGL(cov_mid_kernel, dim3((unsigned)mblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, sigma, gamma,
+  hipLaunchKernelGGL(cov_mid_kernel, dim3((unsigned)mblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, corner, sigma, gamma,
                      status, layout, out, big);
   if (hipGetLastError() != hipSuccess) return -3;
   if (n + 1 <= 32) return 0;
@@ -392,7 +403,7 @@ int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, 
   int64_t blocks = (P + 64 * wpb - 1) / (64 * wpb);  // one 64-pixel chunk per wavefront
   if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(cov_big_kernel, dim3((unsigned)blocks), dim3(64 * wpb), wpb * per_wave, st, n, P, Gh, ldg, dcov,
-                     sigma, gamma, status, layout, out, big);
+                     corner, sigma, gamma, status, layout, out, big);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

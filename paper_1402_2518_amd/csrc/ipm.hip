@@ -116,9 +116,12 @@ struct Px {
     });
   }
 
-  // L D L^T of [[H, 1], [1^T, 0]] (first n rows, border last)
-  __device__ __forceinline__ void factor() {
-    dN = T(0);
+  // L D L^T of [[H, 1], [1^T, corner]] (first n rows, border last); corner
+  // 0 for sum-to-one, -s/nu with the slack pair of sum-lower-than-one, and a
+  // huge negative value when there is no sum row (the border solution is then
+  // zero to rounding)
+  __device__ __forceinline__ void factor(T corner) {
+    dN = corner;
     notpd = false;
     static_for<0, S>([&](auto ss) {
       dinv[ss] = T(1);
@@ -164,7 +167,7 @@ struct Px {
     if (!(dN < T(0)) || !finite(dN)) notpd = true;
   }
 
-  // Solve [[H,1],[1^T,0]] [x; xN] = [r; rN] in place; returns xN.
+  // Solve [[H,1],[1^T,corner]] [x; xN] = [r; rN] in place; returns xN.
   __device__ __forceinline__ T solve(T (&r)[S], T rN) {
     static_for<0, NC>([&](auto kk) {
       constexpr int k = decltype(kk)::value;
@@ -263,8 +266,12 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
   static_for<0, S>([&](auto ss) { bhmax = fmax(bhmax, fabs(bh[ss])); });
   bhmax = gmax<G>(bhmax);
 
-  // interior-point state
-  T a[S], lam[S], nu = T(0);
+  // interior-point state; sum-lower-than-one adds the slack s of 1^T a <= 1
+  // and its multiplier nu as one more complementarity pair, positivity only
+  // has no sum row
+  const bool slo = prm.constraint == kSlo, pos = prm.constraint == kPos;
+  const T inv_np = T(1) / T(n + (slo ? 1 : 0));
+  T a[S], lam[S], nu = slo ? (T)prm.lambda0 : T(0), sl = slo ? inv_np : T(0);
   int it = 0;
   bool start = inrange && !nonfin;
   if constexpr (MODE == kStage2) {
@@ -274,6 +281,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
       start = start && (f & 0x80u);
       it = prm.st_it[p];
       nu = (T)prm.st_nu[p];
+      sl = slo ? (T)prm.st_s[p] : T(0);
     }
     static_for<0, S>([&](auto ss) {
       constexpr int s = decltype(ss)::value;
@@ -283,7 +291,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
     });
   } else {
     static_for<0, S>([&](auto ss) {
-      a[ss] = vm[ss] ? T(1) / T(n) : T(0);
+      a[ss] = vm[ss] ? inv_np : T(0);
       lam[ss] = vm[ss] ? (T)prm.lambda0 : T(0);
     });
   }
@@ -295,6 +303,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
   enum { kIpm = 0, kPol = 1, kDone = 2 };
   int phase = start ? kIpm : kDone;
   bool converged = false, certified = false, cand = false;
+  bool sfree = pos;    // finishing step: no sum row (slack free or no sum constraint)
   uint32_t freem = 0;  // finishing step: bit s set when row s*G+t is free
   int kp = 0;          // finishing-step corrections so far
   T pa[S], pnu = T(0);
@@ -314,8 +323,8 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
         sal = fmaT(a[s], lam[s], sal);
         rdm = fmax(rdm, fabs(rd[s]));
       });
-      rp = gsum<G>(sa) - T(1);
-      mu = gsum<G>(sal) / T(n);
+      rp = pos ? T(0) : gsum<G>(sa) + sl - T(1);
+      mu = (gsum<G>(sal) + sl * nu) * inv_np;
       rdm = gmax<G>(rdm);
       bool conv;
       if constexpr (MODE == kStage1)
@@ -332,6 +341,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
           static_for<0, S>([&](auto ss) {
             if (vm[ss] && a[ss] > lam[ss]) freem |= 1u << ss;
           });
+          sfree = pos || (slo && sl > nu);
         }
       } else if (it >= prm.maxit) {
         flags |= kPxMaxit;
@@ -349,6 +359,15 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
       });
       wa = gmin<G>(wa);
       wl = gmin<G>(wl);
+      // sum-lower-than-one: the slack is one more index (free: its value
+      // 1 - 1^T a must be >= 0; at its bound: the multiplier nu must be)
+      T spa = T(0);
+      static_for<0, S>([&](auto ss) { spa += pa[ss]; });
+      const T sv = T(1) - gsum<G>(spa);
+      const bool slA = slo && sfree && sv < fmin(wa, -tau);
+      const bool slL = slo && !sfree && pnu < fmin(wl, -tau);
+      if (slA) wa = sv;
+      if (slL) wl = pnu;
       if (wa >= -tau && wl >= -tau) {
         certified = true;
         phase = kDone;
@@ -357,8 +376,13 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
           lam[ss] = pl[ss];
         });
         nu = pnu;
+        sl = (slo && sfree) ? sv : T(0);
       } else if (kp >= prm.max_polish) {
         phase = kDone;
+      } else if ((wa < -tau && wa <= wl) ? slA : slL) {
+        sfree = !sfree;
+        ++kp;
+        cand = false;
       } else {
         const bool flipA = (wa < -tau) && (wa <= wl);
         const T target = flipA ? wa : wl;
@@ -386,7 +410,8 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
       D[ss] = vm[ss] ? di : T(0);
     });
     px.form(D);
-    px.factor();
+    const T corner = (phase == kPol) ? (sfree ? -BIG : T(0)) : (pos ? -BIG : (slo ? -sl / nu : T(0)));
+    px.factor(corner);
     if (phase != kDone && px.notpd) {
       if (phase == kIpm) flags |= kPxNotPd;
       phase = kDone;
@@ -396,13 +421,13 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
     T rN;
     if (phase == kPol) {
       static_for<0, S>([&](auto ss) { x[ss] = bh[ss]; });
-      rN = T(1);
+      rN = sfree ? T(0) : T(1);
     } else {
       static_for<0, S>([&](auto ss) { x[ss] = vm[ss] ? -rd[ss] - lam[ss] : T(0); });
-      rN = -rp;
+      rN = slo ? sl - rp : -rp;  // slack pair: + rcs / nu with rcs = s nu
     }
     const bool two = __builtin_amdgcn_ballot_w64(phase == kIpm) != 0;
-    T sig = T(0);
+    T sig = T(0), ds_aff = T(0), dnu_aff = T(0), rcs = T(0);
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
       const T xN = px.solve(x, rN);
@@ -417,12 +442,19 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
         static_for<0, S>([&](auto ss) { dla[ss] = vm[ss] ? -lam[ss] - D[ss] * x[ss] : T(0); });
         T st_aff = fmin(max_step<T, S, G>(a, x, vm), max_step<T, S, G>(lam, dla, vm));
         st_aff = fmin(st_aff, T(1));
+        if (slo) {
+          dnu_aff = xN;
+          ds_aff = -sl - (sl / nu) * dnu_aff;
+          if (ds_aff < T(0)) st_aff = fmin(st_aff, -sl / ds_aff);
+          if (dnu_aff < T(0)) st_aff = fmin(st_aff, -nu / dnu_aff);
+        }
         T smu = T(0);
         static_for<0, S>([&](auto ss) {
           constexpr int s = decltype(ss)::value;
           if (vm[s]) smu = fmaT(a[s] + st_aff * x[s], lam[s] + st_aff * dla[s], smu);
         });
-        const T ratio = (gsum<G>(smu) / T(n)) / mu;
+        const T smu_s = slo ? (sl + st_aff * ds_aff) * (nu + st_aff * dnu_aff) : T(0);
+        const T ratio = ((gsum<G>(smu) + smu_s) * inv_np) / mu;
         sig = ratio * ratio * ratio;
         // corrector right-hand side; dla <- rc / a.  The second-order term
         // is dropped after a short affine step (guards against cycling).
@@ -433,13 +465,19 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
           dla[s] = vm[s] ? rc / a[s] : T(0);
           x[s] = vm[s] ? -rd[s] - dla[s] : T(0);
         });
-        rN = -rp;
+        rcs = slo ? fmaT(soc * ds_aff, dnu_aff, sl * nu) - sig * mu : T(0);
+        rN = slo ? rcs / nu - rp : -rp;
         if (!two) break;
       } else {
         // corrector direction and the common step
         T dl[S];
         static_for<0, S>([&](auto ss) { dl[ss] = vm[ss] ? -dla[ss] - D[ss] * x[ss] : T(0); });
-        const T step = fmin(max_step<T, S, G>(a, x, vm), max_step<T, S, G>(lam, dl, vm));
+        T step = fmin(max_step<T, S, G>(a, x, vm), max_step<T, S, G>(lam, dl, vm));
+        const T ds = slo ? (-rcs - sl * xN) / nu : T(0);
+        if (slo) {
+          if (ds < T(0)) step = fmin(step, -sl / ds);
+          if (xN < T(0)) step = fmin(step, -nu / xN);
+        }
         const T alpha = fmin(T(1), eta * step);
         if (phase == kIpm && finite(alpha)) {
           static_for<0, S>([&](auto ss) {
@@ -447,6 +485,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
             lam[ss] = fmaT(alpha, dl[ss], lam[ss]);
           });
           nu = fmaT(alpha, xN, nu);
+          sl = fmaT(alpha, ds, sl);
         }
         if (phase == kIpm) ++it;
       }
@@ -465,6 +504,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
       });
       if (t == 0) {
         prm.st_nu[p] = (double)nu;
+        if (slo) prm.st_s[p] = (double)sl;
         prm.st_it[p] = it;
         // a loss of positive definiteness in FP32 is retried in FP64 from
         // the last accepted iterate
@@ -480,6 +520,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
         constexpr int s = decltype(ss)::value;
         if (vm[s]) deg |= ((freem >> s) & 1u) ? (a[s] < (T)prm.deg_tol) : (lam[s] < (T)prm.deg_tol);
       });
+      if (slo) deg |= sfree ? (sl < (T)prm.deg_tol) : (nu < (T)prm.deg_tol);
       if (gor_i<G>((int)deg)) flags |= kPxDegenerate;
     }
     double sgm = 1.0;
@@ -504,6 +545,15 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
           }
         }
       });
+      if (prm.dcorner && t == 0) {
+        // corner of the covariance's bordered matrix: 0 on a binding sum row,
+        // -s/nu for the slack pair of an uncertified iterate, -inf without a
+        // sum row
+        double cr;
+        if (certified) cr = sfree ? -(double)INFINITY : 0.0;
+        else cr = pos ? -(double)INFINITY : (slo ? -(double)sl / (double)nu : 0.0);
+        prm.dcorner[p] = cr;
+      }
     }
     if (prm.objective) {
       px.matvec(a, g);

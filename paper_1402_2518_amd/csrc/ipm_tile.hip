@@ -289,7 +289,12 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   static_for<0, C>([&](auto mm) { bhmax = fmax(bhmax, fabs(bh[mm])); });
   bhmax = bmax(bhmax);
 
-  double a[C], lam[C], nu = 0.0;
+  // constraint besides a >= 0: sum-to-one, sum-lower-than-one (slack s of
+  // 1^T a <= 1 with multiplier nu: one more complementarity pair), or
+  // positivity only (no sum row, nu = 0)
+  const bool slo = prm.constraint == kSlo, pos = prm.constraint == kPos;
+  const double inv_np = 1.0 / (n + (slo ? 1 : 0));  // complementarity pairs
+  double a[C], lam[C], nu = slo ? prm.lambda0 : 0.0, s = slo ? inv_np : 0.0;
   int it = 0;
   bool start = inrange && !nonfin;
   if constexpr (MODE == kStage2) {
@@ -299,6 +304,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       start = start && (f & 0x80u);
       it = prm.st_it[p];
       nu = prm.st_nu[p];
+      s = slo ? prm.st_s[p] : 0.0;
     }
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     });
   } else {
     static_for<0, C>([&](auto mm) {
-      a[mm] = vm[mm] ? 1.0 / n : 0.0;
+      a[mm] = vm[mm] ? inv_np : 0.0;
       lam[mm] = vm[mm] ? prm.lambda0 : 0.0;
     });
   }
@@ -319,6 +325,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   enum { kIpm = 0, kPol = 1, kDone = 2 };
   int phase = start ? kIpm : kDone;
   bool converged = false, certified = false, cand = false;
+  bool sfree = pos;  // finishing step: the sum row is absent (slack free or no sum constraint)
   uint32_t freem = 0;  // bit m: compact slot m is free
   int kp = 0;
   double pa[C], pnu = 0.0;
@@ -350,8 +357,8 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
         sal = fmaT(a[m], lam[m], sal);
         rdm = fmax(rdm, fabs(rd[m]));
       });
-      rp = bsum(sa) - 1.0;
-      mu = bsum(sal) * inv_n;
+      rp = pos ? 0.0 : bsum(sa) + s - 1.0;
+      mu = (bsum(sal) + s * nu) * inv_np;
       rdm = bmax(rdm);
       bool conv;
       if constexpr (MODE == kStage1)
@@ -365,6 +372,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
         static_for<0, C>([&](auto mm) {
           if (vm[mm] && a[mm] > lam[mm]) freem |= 1u << mm;
         });
+        sfree = pos || (slo && s > nu);
       } else if (it >= prm.maxit) {
         flags |= kPxMaxit;
         phase = kDone;
@@ -380,6 +388,15 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       });
       wa = bmin(wa);
       wl = bmin(wl);
+      // sum-lower-than-one: the slack is one more index (free: its value
+      // 1 - 1^T a must be >= 0; at its bound: the multiplier nu must be)
+      double spa = 0.0;
+      static_for<0, C>([&](auto mm) { spa += pa[mm]; });
+      const double sv = 1.0 - bsum(spa);
+      const bool slA = slo && sfree && sv < fmin(wa, -tau);
+      const bool slL = slo && !sfree && pnu < fmin(wl, -tau);
+      if (slA) wa = sv;
+      if (slL) wl = pnu;
       if (wa >= -tau && wl >= -tau) {
         certified = true;
         phase = kDone;
@@ -388,8 +405,13 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
           lam[mm] = pl[mm];
         });
         nu = pnu;
+        s = (slo && sfree) ? sv : 0.0;
       } else if (kp >= prm.max_polish) {
         phase = kDone;
+      } else if ((wa < -tau && wa <= wl) ? slA : slL) {
+        sfree = !sfree;
+        ++kp;
+        cand = false;
       } else {
         const bool flipA = (wa < -tau) && (wa <= wl);
         const double target = flipA ? wa : wl;
@@ -453,7 +475,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     const double isu = rcpT(su);
     if (phase == kPol) {
       // equality-constrained problem on the free set: a = w - nu u, 1^T a = 1
-      pnu = (sw - 1.0) * isu;
+      pnu = sfree ? 0.0 : (sw - 1.0) * isu;
       static_for<0, C>([&](auto mm) {
         pa[mm] = (vm[mm] && ((freem >> mm) & 1u)) ? fmaT(-pnu, u[mm], dx[mm]) : 0.0;
       });
@@ -464,7 +486,12 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     if (!two) continue;
 
     // ---- predictor step and centring --------------------------------------
-    const double dnu_aff = (sw + rp) * isu;
+    // sum row: dnu = (1^T w + r_p - rcs/nu) / (1^T u + s/nu) with the slack
+    // pair (rcs = s nu in the predictor), (1^T w + r_p) / 1^T u without it;
+    // none for positivity only; ds = (-rcs - s dnu) / nu
+    const double son = slo ? s / nu : 0.0;
+    const double dnu_aff = pos ? 0.0 : (slo ? (sw + rp - s) / (su + son) : (sw + rp) * isu);
+    const double ds_aff = slo ? -s - son * dnu_aff : 0.0;
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       dx[m] = vm[m] ? fmaT(-dnu_aff, u[m], dx[m]) : 0.0;
@@ -478,12 +505,17 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       st_aff = (vm[m] && dla[m] < 0.0) ? fmin(st_aff, q2) : st_aff;
     });
     st_aff = fmin(bmin(st_aff), 1.0);
+    if (slo) {
+      if (ds_aff < 0.0) st_aff = fmin(st_aff, -s / ds_aff);
+      if (dnu_aff < 0.0) st_aff = fmin(st_aff, -nu / dnu_aff);
+    }
     double smu = 0.0;
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       if (vm[m]) smu = fmaT(a[m] + st_aff * dx[m], lam[m] + st_aff * dla[m], smu);
     });
-    const double ratio = bsum(smu) * inv_n * rcpT(mu);
+    const double smu_s = slo ? (s + st_aff * ds_aff) * (nu + st_aff * dnu_aff) : 0.0;
+    const double ratio = (bsum(smu) + smu_s) * inv_np * rcpT(mu);
     const double sig = ratio * ratio * ratio;
 
     // ---- corrector (second-order term dropped after a short affine step) ---
@@ -500,7 +532,9 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
     double sw2 = 0.0;
     static_for<0, C>([&](auto mm) { sw2 += dx[mm]; });
     sw2 = bsum(sw2);
-    const double dnu = (sw2 + rp) * isu;
+    const double rcs = slo ? fmaT(soc * ds_aff, dnu_aff, s * nu) - sig * mu : 0.0;
+    const double dnu = pos ? 0.0 : (slo ? (sw2 + rp - rcs / nu) / (su + son) : (sw2 + rp) * isu);
+    const double ds = slo ? (-rcs - s * dnu) / nu : 0.0;
     double dl[C];
     static_for<0, C>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -515,6 +549,10 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       step = (vm[m] && dl[m] < 0.0) ? fmin(step, q2) : step;
     });
     step = bmin(step);
+    if (slo) {
+      if (ds < 0.0) step = fmin(step, -s / ds);
+      if (dnu < 0.0) step = fmin(step, -nu / dnu);
+    }
     const double alpha = fmin(1.0, eta * step);
     if (phase == kIpm && fin(alpha)) {
       // the Newton equations give Gh da = -r_d + dlambda - dnu 1 exactly, so
@@ -527,6 +565,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
         lam[m] = fmaT(alpha, dl[m], lam[m]);
       });
       nu = fmaT(alpha, dnu, nu);
+      s = fmaT(alpha, ds, s);
     }
     if (phase == kIpm) ++it;
   }
@@ -538,6 +577,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
       constexpr int m = decltype(mm)::value;
       if (vm[m]) deg |= ((freem >> m) & 1u) ? (a[m] < prm.deg_tol) : (lam[m] < prm.deg_tol);
     });
+    if (slo) deg |= sfree ? (s < prm.deg_tol) : (nu < prm.deg_tol);
     if (bor_i((int)deg)) flags |= kPxDegenerate;
   }
   double sgm = 1.0;
@@ -559,6 +599,15 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
         }
       }
     });
+    if (prm.dcorner && x == 0 && z == 0) {
+      // corner of the bordered matrix of the covariance: 0 on a binding sum
+      // row, -s/nu for the slack pair of an uncertified iterate, -inf when
+      // there is no sum row
+      double cr;
+      if (certified) cr = sfree ? -(double)INFINITY : 0.0;
+      else cr = pos ? -(double)INFINITY : (slo ? -s / nu : 0.0);
+      prm.dcorner[p] = cr;
+    }
   }
   if (prm.objective) {
     tl.to_x(a, xl);

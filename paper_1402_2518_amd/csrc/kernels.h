@@ -23,6 +23,13 @@ enum : uint32_t {
   kPxInexact = 32u,
 };
 
+// Constraint besides a >= 0 (same values as LINMIN_STO / SLO / POS).
+enum : int {
+  kSto = 0,  // 1^T a = 1
+  kSlo = 1,  // 1^T a <= 1
+  kPos = 2,  // none
+};
+
 struct IpmParams {
   int n;                // library size N
   int64_t P;            // pixels in this launch
@@ -33,11 +40,13 @@ struct IpmParams {
   double gamma;         // max_i G_ii
   int maxit;
   int max_polish;
+  int constraint;       // kSto, kSlo or kPos
   double tol_mu, tol_d, tol_p, eta, lambda0, tau, deg_tol, mu_switch;
   // hand-over state between the FP32 and FP64 stages
   double* st_a;         // P x n
   double* st_lam;       // P x n
   double* st_nu;        // P
+  double* st_s;         // P: slack of 1^T a <= 1 (kSlo)
   int32_t* st_it;       // P
   uint8_t* st_flag;     // P (status bits so far; bit 7: still iterating)
   // outputs
@@ -46,6 +55,7 @@ struct IpmParams {
   int32_t* iters;       // P or NULL
   double* objective;    // P or NULL
   double* dcov;         // P x n or NULL: per-coefficient diagonal for the covariance pass
+  double* dcorner;      // P or NULL: corner of the covariance's bordered matrix (-inf: no border)
 };
 
 // ipm.hip: picks the compiled (NC, G) shape for n and precision.
@@ -59,10 +69,11 @@ int launch_quadform_f64(const float* Y, int64_t P, int L, const double* Ci, int 
                         hipStream_t st);
 
 // cov.hip
-// big: P bytes of workspace (pixels routed to the one-wavefront-per-pixel path)
-int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const float* sigma,
-               double gamma, const uint8_t* status_or_null, int layout, double* out_cov, uint8_t* big,
-               hipStream_t st);
+// corner: P values (0: sum row, finite < 0: sum row with that corner, -inf:
+// no sum row); big: P bytes of workspace (pixels routed to larger paths)
+int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const double* corner,
+               const float* sigma, double gamma, const uint8_t* status_or_null, int layout,
+               double* out_cov, uint8_t* big, hipStream_t st);
 
 // setup.hip
 int launch_setup(const float* S_dev, int L, int N, const double* C_dev /* L x L or NULL */,

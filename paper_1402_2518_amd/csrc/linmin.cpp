@@ -58,7 +58,7 @@ void free_lib(linmin_lib l) {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Work {
-  size_t bh, c, dcov, big, st_a, st_lam, st_nu, st_it, st_flag, status, total;
+  size_t bh, c, dcov, dcorner, big, st_a, st_lam, st_nu, st_s, st_it, st_flag, status, total;
 };
 
 Work plan(const linmin_lib_s* lib, int64_t P, const linmin_opts& o, bool want_cov) {
@@ -74,14 +74,16 @@ Work plan(const linmin_lib_s* lib, int64_t P, const linmin_opts& o, bool want_co
   w.c = take(sizeof(double) * p);
   w.dcov = want_cov ? take(sizeof(double) * p * n) : (size_t)-1;
   w.big = want_cov ? take(p) : (size_t)-1;
+  w.dcorner = want_cov ? take(sizeof(double) * p) : (size_t)-1;
   if (o.precision == LINMIN_MIXED) {
     w.st_a = take(sizeof(double) * p * n);
     w.st_lam = take(sizeof(double) * p * n);
     w.st_nu = take(sizeof(double) * p);
+    w.st_s = take(sizeof(double) * p);
     w.st_it = take(sizeof(int32_t) * p);
     w.st_flag = take(p);
   } else {
-    w.st_a = w.st_lam = w.st_nu = w.st_it = w.st_flag = (size_t)-1;
+    w.st_a = w.st_lam = w.st_nu = w.st_s = w.st_it = w.st_flag = (size_t)-1;
   }
   w.status = (o.status == nullptr) ? take(p) : (size_t)-1;
   w.total = off;
@@ -98,6 +100,7 @@ void linmin_default_opts(linmin_opts* o) {
   o->cov_layout = LINMIN_COV_FULL;
   o->maxit = 100;
   o->max_polish = 16;
+  o->constraint = LINMIN_STO;
   o->tol_mu = 1e-13;
   o->tol_d = 1e-12;
   o->tol_p = 1e-13;
@@ -240,6 +243,7 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   if (o.precision != LINMIN_FP64 && o.precision != LINMIN_MIXED) return LINMIN_EINVAL;
   if (o.cov_layout < LINMIN_COV_NONE || o.cov_layout > LINMIN_COV_DIAG) return LINMIN_EINVAL;
   if (o.maxit < 0 || o.max_polish < 0 || !(o.eta > 0.0 && o.eta < 1.0) || !(o.lambda0 > 0.0)) return LINMIN_EINVAL;
+  if (o.constraint != LINMIN_STO && o.constraint != LINMIN_SLO && o.constraint != LINMIN_POS) return LINMIN_EINVAL;
   if (P == 0) return LINMIN_OK;
   if (!cube || !out_coeffs) return LINMIN_EINVAL;
   const bool want_cov = out_cov != nullptr && o.cov_layout != LINMIN_COV_NONE;
@@ -277,6 +281,7 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
     prm.gamma = lib->gamma;
     prm.maxit = o.maxit;
     prm.max_polish = o.max_polish;
+    prm.constraint = o.constraint;
     prm.tol_mu = o.tol_mu;
     prm.tol_d = o.tol_d;
     prm.tol_p = o.tol_p;
@@ -290,10 +295,12 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
     prm.iters = o.iters;
     prm.objective = o.objective;
     prm.dcov = want_cov ? (double*)at(w.dcov) : nullptr;
+    prm.dcorner = want_cov ? (double*)at(w.dcorner) : nullptr;
     if (o.precision == LINMIN_MIXED) {
       prm.st_a = (double*)at(w.st_a);
       prm.st_lam = (double*)at(w.st_lam);
       prm.st_nu = (double*)at(w.st_nu);
+      prm.st_s = (double*)at(w.st_s);
       prm.st_it = (int32_t*)at(w.st_it);
       prm.st_flag = (uint8_t*)at(w.st_flag);
       prm.Gh = lib->Gh32;
@@ -309,8 +316,8 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   }
   if (rc == LINMIN_OK) rc = mark(2);
   if (rc == LINMIN_OK && want_cov)
-    rc = from_launch(lm::launch_cov(lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), sigma, lib->gamma, status,
-                                    o.cov_layout, out_cov, (uint8_t*)at(w.big), st));
+    rc = from_launch(lm::launch_cov(lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), (double*)at(w.dcorner),
+                                    sigma, lib->gamma, status, o.cov_layout, out_cov, (uint8_t*)at(w.big), st));
   if (rc == LINMIN_OK) rc = mark(3);
   if (hipFreeAsync(ws, st) != hipSuccess && rc == LINMIN_OK) rc = LINMIN_EHIP;
   return rc;

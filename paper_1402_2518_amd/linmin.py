@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblinmin.so")
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 COV_NONE, COV_FULL, COV_PACKED, COV_DIAG = 0, 1, 2, 3
+STO, SLO, POS = 0, 1, 2  # sum-to-one, sum-lower-than-one, positivity only
 PX_MAXIT, PX_NONFINITE, PX_BAD_SIGMA, PX_NOT_PD, PX_DEGENERATE, PX_INEXACT = 1, 2, 4, 8, 16, 32
 N_MAX = 128
 
@@ -27,7 +28,8 @@ EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linm
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cov_layout", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("max_polish", ctypes.c_int), ("tol_mu", ctypes.c_double), ("tol_d", ctypes.c_double),
+                ("max_polish", ctypes.c_int), ("constraint", ctypes.c_int), ("tol_mu", ctypes.c_double),
+                ("tol_d", ctypes.c_double),
                 ("tol_p", ctypes.c_double), ("eta", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("tau", ctypes.c_double), ("deg_tol", ctypes.c_double), ("mu_switch", ctypes.c_double),
                 ("status", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("objective", ctypes.c_void_p),
@@ -88,6 +90,7 @@ def default_opts(**kw) -> Opts:
 
 _PREC = {"fp64": FP64, "mixed": MIXED}
 _COV = {None: COV_NONE, "none": COV_NONE, "full": COV_FULL, "packed": COV_PACKED, "diag": COV_DIAG}
+_CONS = {"sto": STO, "slo": SLO, "pos": POS}
 
 
 def _ptr(t):
@@ -172,6 +175,8 @@ class Library:
         _check(status, "status", torch.uint8, P)
         _check(iters, "iters", torch.int32, P)
         _check(objective, "objective", torch.float64, P)
+        if isinstance(opts.get("constraint"), str):
+            opts["constraint"] = _CONS[opts["constraint"]]
         o = default_opts(precision=_PREC[precision], cov_layout=_COV[cov], **opts)
         o.status = None if status is None else status.data_ptr()
         o.iters = None if iters is None else iters.data_ptr()

@@ -44,11 +44,13 @@ def test_constants_match_header():
     assert int(defs["LINMIN_COV_DIAG"]) == linmin.COV_DIAG
     assert int(defs["LINMIN_PX_INEXACT"]) == linmin.PX_INEXACT
     assert int(defs["LINMIN_N_MAX"]) == linmin.N_MAX
+    assert (int(defs["LINMIN_STO"]), int(defs["LINMIN_SLO"]), int(defs["LINMIN_POS"])) == \
+        (linmin.STO, linmin.SLO, linmin.POS)
 
 
 def test_opts_struct_layout():
     # field order and size of linmin_opts as declared in the header
-    assert ctypes.sizeof(linmin.Opts) == 4 * 4 + 8 * 8 + 4 * 8
+    assert ctypes.sizeof(linmin.Opts) == 5 * 4 + 4 + 8 * 8 + 4 * 8  # five ints, padding, doubles, pointers
 
 
 def test_strerror_and_defaults_without_gpu():
@@ -56,6 +58,7 @@ def test_strerror_and_defaults_without_gpu():
     assert lib.linmin_strerror(-4).decode().startswith("matrix not")
     o = linmin.default_opts()
     assert o.maxit == 100 and o.tol_mu == 1e-13 and o.precision == linmin.FP64
+    assert o.constraint == linmin.STO
     h = ctypes.c_void_p()
     # argument errors are reported before any device work
     import numpy as np

@@ -264,3 +264,50 @@ def test_covariance_large_free_sets(dev):
     assert (g3["status"] == oracle.MAXIT).all() and (r3["status"] == oracle.MAXIT).all()
     assert np.abs(g3["a"] - r3["a"]).max() <= 1e-9
     assert _cov_rel_err(g3, r3, np.ones(len(X), bool)) <= 1e-6
+
+
+def _straddling(N, L, P, seed, noise=0.005):
+    """Mixtures whose coefficient sums spread around one (the sum constraint
+    of sum-lower-than-one binds for some pixels only)."""
+    rng = np.random.default_rng(seed)
+    w = synth.custom_workload(N, L, P, seed=seed, n_extra=min(4, N - 1), k_max=max(1, min(4, N - 4)))
+    S = synth.make_library(w)
+    A = rng.dirichlet(np.ones(N), P) * rng.uniform(0.6, 1.4, (P, 1))
+    X = (A @ S.astype(np.float64) + noise * rng.standard_normal((P, L))).astype(np.float32)
+    s = rng.uniform(0.5, 2.0, P).astype(np.float32)
+    return S, X, s
+
+
+@pytest.mark.parametrize("constraint", ["slo", "pos"])
+@pytest.mark.parametrize("N", [8, 36, 48])
+def test_constraint_options(dev, constraint, N):
+    """Sum-lower-than-one and positivity only against the oracle, on the tile
+    kernel (N = 8, 36) and the VALU kernel (N = 48), FP64 and mixed."""
+    _say(f"[gpu] constraint {constraint} N={N}")
+    S, X, s = _straddling(N, max(2 * N, 96), 403, seed=100 + N)
+    code = {"slo": oracle.SLO, "pos": oracle.POS}[constraint]
+    r = oracle.unmix(S, X, s, constraint=code)
+    if constraint == "slo":
+        below = r["a"].sum(1) < 1.0 - 1e-9
+        assert 20 <= below.sum() <= 383, below.sum()
+    for precision in ("fp64", "mixed"):
+        g = _gpu(S, X, s, dev, precision=precision, constraint=constraint)
+        _compare(g, r, a_tol=1e-6 if precision == "fp64" else 1e-3,
+                 f_tol=1e-9 if precision == "fp64" else 1e-4)
+        if constraint == "slo":
+            assert (g["a"].sum(1) <= 1.0 + 1e-9).all()
+
+
+def test_constraint_uncertified_covariance(dev):
+    """Three iterations: the covariance of the last iterate carries the slack
+    corner -s/nu (sum-lower-than-one) or no sum row (positivity only), on both
+    covariance paths (free sets of 12 and of 40 coefficients)."""
+    _say("[gpu] uncertified covariance with the slack corner")
+    for N in (12, 40):
+        S, X, s = _straddling(N, 96, 150, seed=300 + N)
+        for constraint, code in (("slo", oracle.SLO), ("pos", oracle.POS)):
+            g = _gpu(S, X, s, dev, cov="full", constraint=constraint, maxit=3)
+            r = oracle.unmix(S, X, s, constraint=code, maxit=3)
+            assert (g["status"] == oracle.MAXIT).all() and (r["status"] == oracle.MAXIT).all()
+            assert np.abs(g["a"] - r["a"]).max() <= 1e-9
+            assert _cov_rel_err(g, r, np.ones(len(X), bool)) <= 1e-6
