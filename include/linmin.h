@@ -156,6 +156,30 @@ int linmin_library_info(linmin_lib lib, int *L, int *N, double *gamma);
 /* Copy the renormalised Gram matrix G (N x N FP64) to host memory. */
 int linmin_library_gram(linmin_lib lib, double *G_host);
 
+/*
+ * The additional spectra of Sec. 2.5 (listed by name after the references),
+ * which a caller appends to its mineral library so that the fit can absorb
+ * differences of level, slope and large-scale continuum shape between the
+ * pixels and the library.  With t in [0, 1] the position along the spectral
+ * domain (0 at the first channel, 1 at the last), the rows are
+ *   n_extra = 4:  1, 1e-4, t, 1 - t  (flat near one, flat near zero,
+ *                 increasing and decreasing slope);
+ *   n_extra = 12: those four, then cos, sin, -cos, -sin of 2 pi f t for
+ *                 f = 1/4 and then f = 1/2 (periods four and two times the
+ *                 spectral domain; both signs because a >= 0).
+ * The rows are linearly dependent (rank 2 of 4, 6 of 12): with them the
+ * minimiser can be non-unique, and pixels whose free set holds a dependent
+ * group are reported through the status bits.
+ *   L            channels, >= 2.
+ *   n_extra      4 or 12.
+ *   wavelengths  host, L strictly increasing finite values, or NULL for
+ *                equally spaced channels.
+ *   out          host, n_extra x L float32 row-major, caller-owned.
+ * Host only, no device work.  Errors: EINVAL (NULL out, L < 2, n_extra not 4
+ * or 12, wavelengths not finite and increasing).
+ */
+int linmin_extra_spectra(int L, int n_extra, const double *wavelengths, float *out);
+
 /* Release a library (after all work using it has completed). */
 int linmin_destroy_library(linmin_lib lib);
 

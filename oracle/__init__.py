@@ -142,3 +142,29 @@ def unmix(S: np.ndarray, X: np.ndarray, sigma: np.ndarray | None = None,
     if rc != 0:
         raise RuntimeError(f"lo_unmix failed: {rc}")
     return {"a": A, "cov": CV, "F": F, "status": st, "iters": it, "lam": lam, "nu": nu}
+
+
+def extra_spectra(L: int, n: int = 4, wavelengths: np.ndarray | None = None) -> np.ndarray:
+    """The additional spectra of Sec. 2.5, in the order of the table of
+    additional spectra after the references, as an ``n x L`` FP64 array.
+
+    Spectral position ``t`` runs linearly from 0 at the first wavelength to
+    1 at the last (channel index when ``wavelengths`` is None).  The four are
+    a level at one, a level at 1e-4, and slopes ``t`` and ``1 - t``.  The
+    twelve add cosine and sine of periods four and two times the spectral
+    domain (the "1/4" and "1/2" entries: that fraction of a cycle across the
+    domain), each with both signs since the coefficients are non-negative.
+    """
+    if n not in (4, 12):
+        raise ValueError("n must be 4 or 12")
+    if wavelengths is None:
+        w = np.arange(L, dtype=np.float64)
+    else:
+        w = np.asarray(wavelengths, dtype=np.float64)
+    t = (w - w[0]) / (w[-1] - w[0])
+    rows = [np.ones(L), np.full(L, 1e-4), t, 1.0 - t]
+    if n == 12:
+        for cycles in (0.25, 0.5):
+            c, s = np.cos(2 * np.pi * cycles * t), np.sin(2 * np.pi * cycles * t)
+            rows += [c, s, -c, -s]
+    return np.stack(rows)

@@ -239,7 +239,7 @@ struct Tile {
   }
 };
 
-template <int T, int MODE>
+template <int T, int MODE, int CONS>
 __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   using TL = Tile<T>;
   constexpr int NP = TL::NP;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   // constraint besides a >= 0: sum-to-one, sum-lower-than-one (slack s of
   // 1^T a <= 1 with multiplier nu: one more complementarity pair), or
   // positivity only (no sum row, nu = 0)
-  const bool slo = prm.constraint == kSlo, pos = prm.constraint == kPos;
+  constexpr bool slo = CONS == kSlo, pos = CONS == kPos;
   const double inv_np = 1.0 / (n + (slo ? 1 : 0));  // complementarity pairs
   double a[C], lam[C], nu = slo ? prm.lambda0 : 0.0, s = slo ? inv_np : 0.0;
   int it = 0;
@@ -631,17 +631,27 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   }
 }
 
-template <int T>
-static int launch_tile(const IpmParams& p, int mode, hipStream_t st) {
+template <int T, int CONS>
+static int launch_tile_c(const IpmParams& p, int mode, hipStream_t st) {
   const int64_t blocks = (p.P + 15) / 16;
   const dim3 grid((unsigned)blocks), block(256);
   if (mode == kFull)
-    hipLaunchKernelGGL((ipm_tile_kernel<T, kFull>), grid, block, 0, st, p);
+    hipLaunchKernelGGL((ipm_tile_kernel<T, kFull, CONS>), grid, block, 0, st, p);
   else if (mode == kStage2)
-    hipLaunchKernelGGL((ipm_tile_kernel<T, kStage2>), grid, block, 0, st, p);
+    hipLaunchKernelGGL((ipm_tile_kernel<T, kStage2, CONS>), grid, block, 0, st, p);
   else
     return -5;
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int T>
+static int launch_tile(const IpmParams& p, int mode, hipStream_t st) {
+  switch (p.constraint) {
+    case kSto: return launch_tile_c<T, kSto>(p, mode, st);
+    case kSlo: return launch_tile_c<T, kSlo>(p, mode, st);
+    case kPos: return launch_tile_c<T, kPos>(p, mode, st);
+  }
+  return -1;
 }
 
 #if defined(LM_TILE_T)

@@ -5,6 +5,8 @@
 //   create:  setup.hip (C^{-1}, W), gemm.hip (Gram on MFMA), setup.hip (scale)
 //   unmix:   gemm.hip (projections) -> ipm.hip (IPLS + finishing step)
 //            -> cov.hip (covariance)
+// The one host computation is linmin_extra_spectra, which fills a host array
+// a caller appends to its library before linmin_create_library.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdlib.h>
@@ -125,6 +127,37 @@ const char* linmin_strerror(int code) {
     case LINMIN_EUNSUPPORTED: return "unsupported option combination";
     default: return "unknown error";
   }
+}
+
+int linmin_extra_spectra(int L, int n_extra, const double* wavelengths, float* out) {
+  if (!out || L < 2 || (n_extra != 4 && n_extra != 12)) return LINMIN_EINVAL;
+  if (wavelengths) {
+    for (int l = 0; l < L; ++l)
+      if (!isfinite(wavelengths[l]) || (l > 0 && !(wavelengths[l] > wavelengths[l - 1]))) return LINMIN_EINVAL;
+  }
+  const double w0 = wavelengths ? wavelengths[0] : 0.0;
+  const double span = wavelengths ? wavelengths[L - 1] - w0 : (double)(L - 1);
+  const double pi = 3.14159265358979323846;
+  for (int l = 0; l < L; ++l) {
+    // position along the spectral domain, 0 at the first channel, 1 at the last
+    const double t = ((wavelengths ? wavelengths[l] : (double)l) - w0) / span;
+    double v[12];
+    v[0] = 1.0;      // level near one
+    v[1] = 1e-4;     // level near zero
+    v[2] = t;        // increasing slope
+    v[3] = 1.0 - t;  // decreasing slope
+    for (int k = 0; k < 2; ++k) {
+      // periods four and two times the domain: a quarter and a half cycle
+      const double ph = 2.0 * pi * (k == 0 ? 0.25 : 0.5) * t;
+      const double c = cos(ph), sn = sin(ph);
+      v[4 + 4 * k] = c;
+      v[5 + 4 * k] = sn;
+      v[6 + 4 * k] = -c;
+      v[7 + 4 * k] = -sn;
+    }
+    for (int i = 0; i < n_extra; ++i) out[(size_t)i * L + l] = (float)v[i];
+  }
+  return LINMIN_OK;
 }
 
 int linmin_create_library(const float* S, int L, int N, const double* noise_cov, linmin_lib* out) {

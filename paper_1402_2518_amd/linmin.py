@@ -23,7 +23,8 @@ PX_MAXIT, PX_NONFINITE, PX_BAD_SIGMA, PX_NOT_PD, PX_DEGENERATE, PX_INEXACT = 1, 
 N_MAX = 128
 
 EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linmin_workspace_bytes",
-           "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror")
+           "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror",
+           "linmin_extra_spectra")
 
 
 class Opts(ctypes.Structure):
@@ -68,6 +69,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.linmin_library_gram.restype = ctypes.c_int
         lib.linmin_destroy_library.argtypes = [vp]
         lib.linmin_destroy_library.restype = ctypes.c_int
+        lib.linmin_extra_spectra.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp]
+        lib.linmin_extra_spectra.restype = ctypes.c_int
         lib.linmin_strerror.argtypes = [ctypes.c_int]
         lib.linmin_strerror.restype = ctypes.c_char_p
         _lib = lib
@@ -86,6 +89,20 @@ def default_opts(**kw) -> Opts:
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
+
+
+def extra_spectra(L: int, n: int = 4, wavelengths=None) -> np.ndarray:
+    """The additional spectra of Sec. 2.5 (``n`` = 4 or 12) as an ``n x L``
+    float32 array, from ``linmin_extra_spectra``."""
+    out = np.empty((n, L), np.float32)
+    wl = None if wavelengths is None else np.ascontiguousarray(wavelengths, dtype=np.float64)
+    if wl is not None and wl.shape != (L,):
+        raise ValueError("wavelengths must hold L values")
+    rc = load().linmin_extra_spectra(int(L), int(n), None if wl is None else wl.ctypes.data_as(ctypes.c_void_p),
+                                     out.ctypes.data_as(ctypes.c_void_p))
+    if rc != OK:
+        raise LinminError(rc, "linmin_extra_spectra")
+    return out
 
 
 _PREC = {"fp64": FP64, "mixed": MIXED}

@@ -29,12 +29,12 @@ mapped onto [lo, hi] with lo ~ U[0.1, 0.45], hi ~ U[lo+0.05, 0.6], multiplied
 by 1-4 Gaussian absorption bands ``1 - d exp(-(j-c)^2 / (2 w^2))`` with depth
 d ~ U[0.05, 0.4], width w ~ U[2, 8] channels and centre c ~ U[0, L-1].  The four
 extra spectra (flat, slope and two broad smooth curves) stand in for the
-paper's additional continuum spectra (Sec. 2.5).
+paper's additional continuum spectra (Sec. 2.5); the paper's exact sets of 4
+and 12 are a library builder of the product, not an input recipe.
 """
 from __future__ import annotations
 
 import dataclasses
-import math
 
 import numpy as np
 
@@ -98,28 +98,6 @@ def extra_spectra(L: int) -> np.ndarray:
         np.exp(-((x - 0.3) ** 2) / (2 * 0.35 ** 2)),
         np.exp(-((x - 0.8) ** 2) / (2 * 0.4 ** 2)),
     ])
-
-
-def paper_extra_spectra(L: int, n: int = 4) -> np.ndarray:
-    """The paper's additional spectra (Sec. 2.5 and the Appendix table).
-
-    ``n = 4``: flat 1, flat 0.0001, slope increasing, slope decreasing.
-    ``n = 12``: those plus +-cos and +-sin whose periods are 1/4 and 1/2 of
-    the spectral domain length, offset to stay positive.  The slopes run
-    between 0 and 1.  These four span only two dimensions (the flats and the
-    slopes are pairwise affinely dependent), which makes the minimiser
-    non-unique on some pixels.
-    """
-    x = np.arange(L, dtype=np.float64) / max(L - 1, 1)
-    rows = [np.ones(L), np.full(L, 1e-4), x, 1.0 - x]
-    if n == 12:
-        for frac in (0.25, 0.5):
-            ph = 2 * math.pi * x / frac
-            rows += [0.5 + 0.5 * np.cos(ph), 0.5 + 0.5 * np.sin(ph),
-                     0.5 - 0.5 * np.cos(ph), 0.5 - 0.5 * np.sin(ph)]
-    elif n != 4:
-        raise ValueError("n must be 4 or 12")
-    return np.stack(rows)
 
 
 def make_library(w: Workload | str) -> np.ndarray:

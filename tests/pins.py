@@ -221,3 +221,18 @@ def brute_force_pos(G: np.ndarray, B: np.ndarray, tol: float = 1e-12) -> np.ndar
             best[take] = f[take]
             A[take] = a[take]
     return A
+
+
+def objective_gap_bound(S, x, s, l1, pairs, tol_mu=1e-13, tol_d=1e-12):
+    """Largest excess of the eq. 2 objective over s^2 at an interior iterate
+    that met the stopping tests, over the least value.  For the convex QP,
+    q(a) - q(a*) <= grad q(a)^T (a - a*) = r_d^T (a - a*) + lam^T a
+    - lam^T a* - nu (1^T a - 1^T a*), with lam^T a* >= 0; so the scaled gap is
+    at most pairs mu + ||r_d||_inf ||a - a*||_1 (plus nu r_p, of the order of
+    tol_p times a unit multiplier, folded into the slack).  ``l1`` bounds
+    ||a - a*||_1; the objective is 2 gamma q / s^2 plus a constant."""
+    Sd = np.asarray(S, np.float64)
+    gam = float((Sd * Sd).sum(1).max())
+    bh = np.abs(Sd @ np.asarray(x, np.float64)).max() / gam
+    q = pairs * tol_mu + tol_d * (1.0 + bh) * l1 + 1e-13
+    return 2.0 * gam * q / float(s) ** 2

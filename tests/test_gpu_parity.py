@@ -311,3 +311,48 @@ def test_constraint_uncertified_covariance(dev):
             assert (g["status"] == oracle.MAXIT).all() and (r["status"] == oracle.MAXIT).all()
             assert np.abs(g["a"] - r["a"]).max() <= 1e-9
             assert _cov_rel_err(g, r, np.ones(len(X), bool)) <= 1e-6
+
+
+@pytest.mark.parametrize("n_extra", [4, 12])
+@pytest.mark.parametrize("constraint", ["sto", "slo", "pos"])
+def test_paper_extra_library(dev, constraint, n_extra):
+    """Libraries carrying the paper's additional spectra (Sec. 2.5): 32
+    minerals plus 4 (N = 36, tile kernel) or 12 (N = 44, VALU kernel).  The
+    extras are linearly dependent, so the minimiser may be non-unique; the
+    least objective is unique.  Compared: the objective, within the bound on
+    an interior iterate's excess (complementarity gap and dual residual)
+    where either side is uncertified; coefficients and covariance where
+    both sides certified a strictly complementary solution (then the
+    minimiser is unique); feasibility everywhere."""
+    from paper_1402_2518_amd import linmin
+    _say(f"[gpu] paper extra library n_extra={n_extra} {constraint}")
+    w = synth.WORKLOADS["orbital"]
+    M = synth.make_library(w)[:32]
+    S_g = np.concatenate([M, linmin.extra_spectra(w.L, n_extra)])
+    S_o = np.concatenate([M, oracle.extra_spectra(w.L, n_extra).astype(np.float32)])
+    assert np.abs(S_g.view(np.int32).astype(np.int64) - S_o.view(np.int32).astype(np.int64)).max() <= 1
+    X, s = synth.make_cube(w, p0=5000, p1=5600)
+    code = {"sto": oracle.STO, "slo": oracle.SLO, "pos": oracle.POS}[constraint]
+    r = oracle.unmix(S_o, X, s, constraint=code)
+    pairs = len(S_o) + (1 if constraint == "slo" else 0)
+    for precision in ("fp64", "mixed"):
+        g = _gpu(S_g, X, s, dev, precision=precision, constraint=constraint)
+        assert np.isfinite(g["a"]).all() and (g["a"] >= 0).all()
+        tot = g["a"].sum(1)
+        if constraint == "sto":
+            assert np.abs(tot - 1).max() <= 1e-12
+        elif constraint == "slo":
+            assert tot.max() <= 1 + 1e-12
+        exact = (g["status"] == 0) & (r["status"] == 0)
+        loose = ((g["status"] | r["status"]) & oracle.INEXACT) != 0
+        gap = np.array([pins.objective_gap_bound(S_o, X[p], s[p], g["a"][p].sum() + r["a"][p].sum(), pairs)
+                        for p in range(len(X))])
+        rnd = 1e-9 if precision == "fp64" else 1e-4
+        dF = np.abs(g["objective"] - r["F"])
+        lim = np.where(loose, gap, 0.0) + rnd * r["F"]
+        assert (dF <= lim).all(), float((dF / lim).max())
+        if exact.any():
+            da = np.abs(g["a"][exact] - r["a"][exact]).max()
+            assert da <= (1e-6 if precision == "fp64" else 1e-3), da
+            assert _cov_rel_err(g, r, exact) <= (1e-6 if precision == "fp64" else 1e-3)
+        _say(f"  {precision}: certified both {exact.sum()}/{len(X)}, inexact either {loose.sum()}")

@@ -40,11 +40,3 @@ def test_tiny_workload():
     assert X.shape == (1000, 64) and (s == np.float32(0.005)).all()
     k = (A > 0).sum(1)
     assert k.min() == 1 and k.max() == 3
-
-
-def test_paper_extra_spectra():
-    E4 = synth.paper_extra_spectra(110, 4)
-    assert E4.shape == (4, 110)
-    assert np.linalg.matrix_rank(E4) == 2
-    E12 = synth.paper_extra_spectra(110, 12)
-    assert E12.shape == (12, 110) and E12.min() >= 0
