@@ -180,6 +180,66 @@ int linmin_library_gram(linmin_lib lib, double *G_host);
  */
 int linmin_extra_spectra(int L, int n_extra, const double *wavelengths, float *out);
 
+/*
+ * Batches: many cubes, each with its own library (any sizes), unmixed by a
+ * few fused launches instead of one sequence of launches per cube.  Pixels
+ * are independent (eq. 2 is a sum over pixels), so a batch computes for
+ * every cube exactly what linmin_unmix computes for it alone.
+ *
+ * One cube of a batch: the arguments of linmin_unmix, with the per-pixel
+ * arrays that linmin_opts carries for a single call.  Every pointer is
+ * device memory (NULL where linmin_unmix allows NULL); out_cov is filled in
+ * the layout of the batch's opts->cov_layout.
+ */
+typedef struct {
+    linmin_lib lib;
+    const float *cube;   /* P x L */
+    int64_t P;           /* >= 0; P == 0 makes the job a no-op */
+    const float *sigma;  /* P, or NULL for s_p = 1 */
+    double *out_coeffs;  /* P x N */
+    double *out_cov;     /* per the batch's cov_layout, or NULL */
+    uint8_t *status;     /* P, or NULL */
+    int32_t *iters;      /* P, or NULL */
+    double *objective;   /* P, or NULL */
+} linmin_job;
+
+typedef struct linmin_batch_s *linmin_batch;
+
+/*
+ * Plan a batch.  Synchronous on the current device: checks every job,
+ * groups the cubes by compiled kernel (projection width, interior-point
+ * shape), allocates the work areas of all cubes in one device buffer and
+ * uploads one job table per launch.  Afterwards linmin_batch_run enqueues
+ * the fused launches only: no allocation, no host-to-device copy, so a run
+ * may be captured in a HIP graph.
+ *   jobs, n_jobs  host array of n_jobs >= 0 jobs (copied; the buffers they
+ *                 point to are not, and must stay valid for every run).
+ *   opts          NULL for defaults; its precision, layout, constraint and
+ *                 tolerances apply to every job; its status / iters /
+ *                 objective members are ignored (each job carries its own);
+ *                 stage_events, if set, are recorded by every run.
+ * The libraries must outlive the batch.  Errors: EINVAL (NULL out, a job
+ * with a NULL library or a library of another device, P < 0, NULL cube or
+ * out_coeffs with P > 0), EUNSUPPORTED, ENOMEM, EHIP.
+ */
+int linmin_batch_create(const linmin_job *jobs, int n_jobs, const linmin_opts *opts, linmin_batch *out);
+
+/*
+ * Enqueue every job of the batch on stream (NULL: the default stream):
+ * projections, interior-point solves and covariance, each stage as one
+ * launch per compiled shape over all cubes of that shape.  Asynchronous like
+ * a kernel launch.  Runs of one batch share its work areas: two runs in
+ * flight at once on different streams race.  Errors: EINVAL (NULL batch,
+ * other device current), EHIP.
+ */
+int linmin_batch_run(linmin_batch batch, void *stream);
+
+/* Device bytes the batch holds (work areas and job tables); 0 for NULL. */
+size_t linmin_batch_device_bytes(linmin_batch batch);
+
+/* Release a batch (after all its runs have completed). */
+int linmin_batch_destroy(linmin_batch batch);
+
 /* Release a library (after all work using it has completed). */
 int linmin_destroy_library(linmin_lib lib);
 

@@ -209,4 +209,35 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// Batched launches over several cubes: job j owns the units [start[j],
+// start[j + 1]) of the launch (blocks, or pixel chunks of grid-stride
+// kernels); start holds njobs + 1 ascending values.  The unit index is
+// uniform, so the search runs on the scalar unit.
+__device__ __forceinline__ int job_of(const int64_t* __restrict__ start, int njobs, int64_t u) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Copy of a job descriptor that every lane reads at the same address, marked
+// wave-uniform word by word so that its fields live in scalar registers.
+template <typename S>
+__device__ __forceinline__ S uniform_copy(const S* __restrict__ p) {
+  static_assert(sizeof(S) % 4 == 0, "descriptor size must be a multiple of 4 bytes");
+  constexpr int W = (int)(sizeof(S) / 4);
+  uint32_t w[W];
+  __builtin_memcpy(w, p, sizeof(S));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  S out;
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
 }  // namespace lm

@@ -221,68 +221,82 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
 }
 
 // every pixel; those with |I| + 1 > 16 are flagged for the next paths
-__global__ __launch_bounds__(256) void cov_small_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
-                                                        const double* __restrict__ dcov,
-                                                        const double* __restrict__ corner,
-                                                        const float* __restrict__ sigma, double gamma,
-                                                        const uint8_t* __restrict__ status, int layout,
-                                                        double* __restrict__ out, uint8_t* __restrict__ big) {
+__device__ __forceinline__ void cov_small_body(const CovJob& J, int64_t blk) {
   __shared__ double dvs[16][16];
   __shared__ int idxs[16][16];
   const int g = threadIdx.x >> 4;
-  const int64_t p = (int64_t)blockIdx.x * 16 + g;
-  cov_group<16>(n, p, p < P, Gh, ldg, dcov, corner, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
+  const int64_t p = blk * 16 + g;
+  cov_group<16>(J.n, p, p < J.P, J.Gh, J.ldg, J.dcov, J.corner, J.sigma, J.gamma, J.status, J.layout, J.out, J.big,
+                dvs[g], idxs[g]);
 }
 
-// flagged pixels only, four per wavefront: each wavefront takes 64 flags at a
-// time and hands the set ones to its rows in order
-__global__ __launch_bounds__(256, 2) void cov_mid_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
-                                                      const double* __restrict__ dcov,
-                                                      const double* __restrict__ corner,
-                                                      const float* __restrict__ sigma, double gamma,
-                                                      const uint8_t* __restrict__ status, int layout,
-                                                      double* __restrict__ out, uint8_t* __restrict__ big) {
-  __shared__ double dvs[16][32];
-  __shared__ int idxs[16][32];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(256) void cov_small_kernel(CovJob J) { cov_small_body(J, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void cov_small_batch_kernel(const CovJob* __restrict__ jobs,
+                                                              const int64_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const CovJob J = uniform_copy(jobs + j);
+  cov_small_body(J, (int64_t)blockIdx.x - start[j]);
+}
+
+// flagged pixels only, four per wavefront: the wavefront takes the 64 flags
+// of the chunk at base and hands the set ones to its rows in order
+__device__ __forceinline__ void cov_mid_chunk(const CovJob& J, int64_t base, double (*dvs)[32], int (*idxs)[32]) {
+  const int lane = threadIdx.x & 63;
   const int g = threadIdx.x >> 4, gi = (lane >> 4) & 3;
-  const int wpb = blockDim.x >> 6;
-  const int64_t nw = (int64_t)gridDim.x * wpb;
-  for (int64_t base = ((int64_t)blockIdx.x * wpb + wave) * 64; base < P; base += nw * 64) {
-    const bool flagged = base + lane < P && big[base + lane] != 0;
-    uint64_t todo = __builtin_amdgcn_ballot_w64(flagged);
-    while (todo) {
-      uint64_t rest = todo;
-      for (int k = 0; k < gi; ++k) rest &= rest - 1ull;
-      const bool has = rest != 0ull;
-      const int64_t p = base + (has ? __builtin_ctzll(rest) : 0);
-      cov_group<32>(n, p, has, Gh, ldg, dcov, corner, sigma, gamma, status, layout, out, big, dvs[g], idxs[g]);
-      for (int k = 0; k < 4; ++k) todo &= todo - 1ull;
-    }
+  const bool flagged = base + lane < J.P && J.big[base + lane] != 0;
+  uint64_t todo = __builtin_amdgcn_ballot_w64(flagged);
+  while (todo) {
+    uint64_t rest = todo;
+    for (int k = 0; k < gi; ++k) rest &= rest - 1ull;
+    const bool has = rest != 0ull;
+    const int64_t p = base + (has ? __builtin_ctzll(rest) : 0);
+    cov_group<32>(J.n, p, has, J.Gh, J.ldg, J.dcov, J.corner, J.sigma, J.gamma, J.status, J.layout, J.out, J.big,
+                  dvs[g], idxs[g]);
+    for (int k = 0; k < 4; ++k) todo &= todo - 1ull;
   }
 }
 
-__global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const double* __restrict__ Gh, int ldg,
-                                                      const double* __restrict__ dcov,
-                                                      const double* __restrict__ corner,
-                                                      const float* __restrict__ sigma, double gamma,
-                                                      const uint8_t* __restrict__ status, int layout,
-                                                      double* __restrict__ out, const uint8_t* __restrict__ big) {
-  extern __shared__ double smem[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int q_max = n + 1;
-  double* A = smem + wave * (q_max * q_max + 4 * q_max);  // q x q, column-major (ld = q)
-  double* colk = A + q_max * q_max;                      // pivot column before the step
-  double* dv = colk + q_max;                             // d of the included indices, by position
-  int* idx = (int*)(dv + q_max);                         // included index at each position
+__global__ __launch_bounds__(256, 2) void cov_mid_kernel(CovJob J) {
+  __shared__ double dvs[16][32];
+  __shared__ int idxs[16][32];
+  const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  for (int64_t base = ((int64_t)blockIdx.x * wpb + wave) * 64; base < J.P; base += nw * 64)
+    cov_mid_chunk(J, base, dvs, idxs);
+}
+
+// chunks u in [0, start[njobs]) over the jobs, 64 pixels each
+__global__ __launch_bounds__(256, 2) void cov_mid_batch_kernel(const CovJob* __restrict__ jobs,
+                                                               const int64_t* __restrict__ start, int njobs) {
+  __shared__ double dvs[16][32];
+  __shared__ int idxs[16][32];
+  const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * wpb, total = start[njobs];
+  for (int64_t u = (int64_t)blockIdx.x * wpb + wave; u < total; u += nw) {
+    const int j = job_of(start, njobs, u);
+    const CovJob J = uniform_copy(jobs + j);
+    cov_mid_chunk(J, (u - start[j]) * 64, dvs, idxs);
+  }
+}
+
+// one wavefront per pixel in LDS for what the register paths left: the
+// wavefront's slot holds a qcap x qcap matrix and three qcap vectors
+__device__ __forceinline__ void cov_big_chunk(const CovJob& J, int64_t base, double* slot, int qcap) {
+  const int lane = threadIdx.x & 63;
+  const int n = J.n, ldg = J.ldg, layout = J.layout;
+  const double* __restrict__ Gh = J.Gh;
+  const double* __restrict__ dcov = J.dcov;
+  double* __restrict__ out = J.out;
+  double* A = slot;                  // q x q, column-major (ld = q)
+  double* colk = A + qcap * qcap;    // pivot column before the step
+  double* dv = colk + qcap;          // d of the included indices, by position
+  int* idx = (int*)(dv + qcap);      // included index at each position
   const double qnan = __builtin_nan("");
   const int64_t per = layout == 1 ? (int64_t)n * n : (layout == 2 ? (int64_t)n * (n + 1) / 2 : n);
   const int j0 = lane, j1 = lane + 64;  // the output columns of this lane
-
-  const int wpb = blockDim.x >> 6;
-  const int64_t nw = (int64_t)gridDim.x * wpb;
-  for (int64_t base = ((int64_t)blockIdx.x * wpb + wave) * 64; base < P; base += nw * 64) {
-    const bool flagged = base + lane < P && big[base + lane];
+  {
+    const bool flagged = base + lane < J.P && J.big[base + lane];
     uint64_t todo = __builtin_amdgcn_ballot_w64(flagged);
     while (todo) {
       const int64_t p = base + __builtin_ctzll(todo);
@@ -290,13 +304,13 @@ __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const do
       const double d0 = j0 < n ? dcov[p * n + j0] : 0.0;
       const double d1 = j1 < n ? dcov[p * n + j1] : 0.0;
       double* o = out + p * per;
-      bool bad = status && (status[p] & (kPxNonfinite | kPxBadSigma));
-      const double s = sigma ? (double)sigma[p] : 1.0;
+      bool bad = J.status && (J.status[p] & (kPxNonfinite | kPxBadSigma));
+      const double s = J.sigma ? (double)J.sigma[p] : 1.0;
       if (!(s > 0.0) || !isfin(s)) bad = true;
       const bool in0 = j0 < n && isfin(d0), in1 = j1 < n && isfin(d1);
       const uint64_t lo = __builtin_amdgcn_ballot_w64(in0), hi = __builtin_amdgcn_ballot_w64(in1);
       const int m = __builtin_popcountll(lo) + __builtin_popcountll(hi);
-      const double cval = corner[p];
+      const double cval = J.corner[p];
       const int bord = cval == -(double)INFINITY ? 0 : 1;
       const int q = m + bord;
       const int r0 = rank128(lo, hi, j0), r1 = rank128(lo, hi, j1);
@@ -358,7 +372,7 @@ __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const do
         lds_sync();
       }
       const bool nanout = bad || singular;
-      const double scale = -s * s / gamma;
+      const double scale = -s * s / J.gamma;
       if (layout == 3) {
         if (j0 < n) o[j0] = nanout ? qnan : (in0 ? scale * A[r0 * q + r0] : 0.0);
         if (j1 < n) o[j1] = nanout ? qnan : (in1 ? scale * A[r1 * q + r1] : 0.0);
@@ -378,33 +392,85 @@ __global__ __launch_bounds__(256) void cov_big_kernel(int n, int64_t P, const do
   }
 }
 
+__global__ __launch_bounds__(256) void cov_big_kernel(CovJob J) {
+  extern __shared__ double smem[];
+  const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  const int qcap = J.n + 1;
+  double* slot = smem + wave * (qcap * qcap + 4 * qcap);
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  for (int64_t base = ((int64_t)blockIdx.x * wpb + wave) * 64; base < J.P; base += nw * 64)
+    cov_big_chunk(J, base, slot, qcap);
+}
+
+__global__ __launch_bounds__(256) void cov_big_batch_kernel(const CovJob* __restrict__ jobs,
+                                                            const int64_t* __restrict__ start, int njobs, int qcap) {
+  extern __shared__ double smem[];
+  const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  double* slot = smem + wave * (qcap * qcap + 4 * qcap);
+  const int64_t nw = (int64_t)gridDim.x * wpb, total = start[njobs];
+  for (int64_t u = (int64_t)blockIdx.x * wpb + wave; u < total; u += nw) {
+    const int j = job_of(start, njobs, u);
+    const CovJob J = uniform_copy(jobs + j);
+    cov_big_chunk(J, (u - start[j]) * 64, slot, qcap);
+  }
+}
+
+// LDS bytes of one wavefront of the big path for borders up to qcap
+static size_t big_slot_bytes(int qcap) { return sizeof(double) * (size_t)(qcap * qcap + 4 * qcap); }
+
+// wavefronts per workgroup of the big path: up to 4, at most 64 KB per workgroup
+static int big_waves(int qcap) {
+  int wpb = (int)((64 * 1024) / big_slot_bytes(qcap));
+  if (wpb > 4) wpb = 4;
+  if (wpb < 1) wpb = 1;
+  return wpb;
+}
+
 int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const double* corner,
                const float* sigma, double gamma, const uint8_t* status, int layout, double* out, uint8_t* big,
                hipStream_t st) {
   if (P <= 0) return 0;
   if (n < 1 || n > 128) return -5;
+  const CovJob J{n, P, Gh, ldg, dcov, corner, sigma, gamma, status, layout, out, big};
   const int64_t sblocks = (P + 15) / 16;
-  hipLaunchKernelGGL(cov_small_kernel, dim3((unsigned)sblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, corner, sigma, gamma,
-                     status, layout, out, big);
+  hipLaunchKernelGGL(cov_small_kernel, dim3((unsigned)sblocks), dim3(256), 0, st, J);
   if (hipGetLastError() != hipSuccess) return -3;
   if (n + 1 <= 16) return 0;  // every pixel fit the first path
   int64_t mblocks = (P + 4 * 64 - 1) / (4 * 64);
   if (mblocks > 4096) mblocks = 4096;
-  hipLaunchKernelGGL(cov_mid_kernel, dim3((unsigned)mblocks), dim3(256), 0, st, n, P, Gh, ldg, dcov, corner, sigma, gamma,
-                     status, layout, out, big);
+  hipLaunchKernelGGL(cov_mid_kernel, dim3((unsigned)mblocks), dim3(256), 0, st, J);
   if (hipGetLastError() != hipSuccess) return -3;
   if (n + 1 <= 32) return 0;
-  const int q_max = n + 1;
-  const size_t per_wave = sizeof(double) * (size_t)(q_max * q_max + 4 * q_max);
-  int wpb = (int)((64 * 1024) / per_wave);  // up to 4 waves, at most 64 KB per workgroup
-  if (wpb > 4) wpb = 4;
-  if (wpb < 1) wpb = 1;
-  if (per_wave * wpb > 160 * 1024) return -5;
+  const int qcap = n + 1, wpb = big_waves(qcap);
+  if (big_slot_bytes(qcap) * wpb > 160 * 1024) return -5;
   int64_t blocks = (P + 64 * wpb - 1) / (64 * wpb);  // one 64-pixel chunk per wavefront
   if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(cov_big_kernel, dim3((unsigned)blocks), dim3(64 * wpb), wpb * per_wave, st, n, P, Gh, ldg, dcov,
-                     corner, sigma, gamma, status, layout, out, big);
+  hipLaunchKernelGGL(cov_big_kernel, dim3((unsigned)blocks), dim3(64 * wpb), wpb * big_slot_bytes(qcap), st, J);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_cov_batch(const CovBatch& small, const CovBatch& mid, const CovBatch& big, hipStream_t st) {
+  if (small.njobs > 0 && small.units > 0) {
+    hipLaunchKernelGGL(cov_small_batch_kernel, dim3((unsigned)small.units), dim3(256), 0, st, small.jobs, small.start,
+                       small.njobs);
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  if (mid.njobs > 0 && mid.units > 0) {
+    int64_t mblocks = (mid.units + 3) / 4;
+    if (mblocks > 4096) mblocks = 4096;
+    hipLaunchKernelGGL(cov_mid_batch_kernel, dim3((unsigned)mblocks), dim3(256), 0, st, mid.jobs, mid.start, mid.njobs);
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  if (big.njobs > 0 && big.units > 0) {
+    const int qcap = big.qcap, wpb = big_waves(qcap);
+    if (qcap < 2 || qcap > 129 || big_slot_bytes(qcap) * wpb > 160 * 1024) return -5;
+    int64_t blocks = (big.units + wpb - 1) / wpb;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(cov_big_batch_kernel, dim3((unsigned)blocks), dim3(64 * wpb), wpb * big_slot_bytes(qcap), st,
+                       big.jobs, big.start, big.njobs, qcap);
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  return 0;
 }
 
 }  // namespace lm

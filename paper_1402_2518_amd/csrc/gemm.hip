@@ -17,12 +17,12 @@ namespace lm {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int NT>
-__global__ __launch_bounds__(256) void gemm_proj_f64(const float* __restrict__ Y, int64_t P, int L,
-                                                     const double* __restrict__ W, int ldw, int N,
-                                                     double* __restrict__ B, double* __restrict__ c) {
+__device__ __forceinline__ void gemm_proj_body(const float* __restrict__ Y, int64_t P, int L,
+                                               const double* __restrict__ W, int ldw, int N,
+                                               double* __restrict__ B, double* __restrict__ c, int64_t blk) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int64_t p0 = (blk * 4 + wave) * 16;
   if (p0 >= P) return;
   const int row = lane & 15, g = lane >> 4;
   const int64_t p = p0 + row;
@@ -67,14 +67,30 @@ __global__ __launch_bounds__(256) void gemm_proj_f64(const float* __restrict__ Y
   }
 }
 
+template <int NT>
+__global__ __launch_bounds__(256) void gemm_proj_f64(const float* __restrict__ Y, int64_t P, int L,
+                                                     const double* __restrict__ W, int ldw, int N,
+                                                     double* __restrict__ B, double* __restrict__ c) {
+  gemm_proj_body<NT>(Y, P, L, W, ldw, N, B, c, blockIdx.x);
+}
+
+// Several cubes in one launch (libraries with the same column-block count).
+template <int NT>
+__global__ __launch_bounds__(256) void gemm_proj_batch_f64(const ProjJob* __restrict__ jobs,
+                                                           const int64_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const ProjJob J = uniform_copy(jobs + j);
+  gemm_proj_body<NT>(J.Y, J.P, J.L, J.W, J.ldw, J.N, J.B, J.c, (int64_t)blockIdx.x - start[j]);
+}
+
 // c[p] = y_p^T Ci y_p for a full L x L inverse noise covariance Ci (ldc
 // columns, zero padded): MFMA tiles of (Y Ci) dotted with Y on the fly.
-__global__ __launch_bounds__(256) void quadform_f64(const float* __restrict__ Y, int64_t P, int L,
-                                                    const double* __restrict__ Ci, int ldc,
-                                                    double* __restrict__ c) {
+__device__ __forceinline__ void quadform_body(const float* __restrict__ Y, int64_t P, int L,
+                                              const double* __restrict__ Ci, int ldc, double* __restrict__ c,
+                                              int64_t blk) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int64_t p0 = (blk * 4 + wave) * 16;
   if (p0 >= P) return;
   const int row = lane & 15, g = lane >> 4;
   const int64_t p = p0 + row;
@@ -114,6 +130,19 @@ __global__ __launch_bounds__(256) void quadform_f64(const float* __restrict__ Y,
   }
 }
 
+__global__ __launch_bounds__(256) void quadform_f64(const float* __restrict__ Y, int64_t P, int L,
+                                                    const double* __restrict__ Ci, int ldc,
+                                                    double* __restrict__ c) {
+  quadform_body(Y, P, L, Ci, ldc, c, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void quadform_batch_f64(const ProjJob* __restrict__ jobs,
+                                                          const int64_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const ProjJob J = uniform_copy(jobs + j);
+  quadform_body(J.Y, J.P, J.L, J.Ci, J.ldc, J.c, (int64_t)blockIdx.x - start[j]);
+}
+
 int launch_gemm_proj_f64(const float* Y, int64_t P, int L, const double* W, int ldw, int N,
                          double* B, double* c, hipStream_t st) {
   if (P <= 0) return 0;
@@ -135,6 +164,29 @@ int launch_quadform_f64(const float* Y, int64_t P, int L, const double* Ci, int 
   if (P <= 0) return 0;
   const int64_t blocks = (P + 63) / 64;
   hipLaunchKernelGGL(quadform_f64, dim3((unsigned)blocks), dim3(256), 0, st, Y, P, L, Ci, ldc, c);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int proj_pixels_per_block() { return 64; }
+
+int launch_gemm_proj_batch(int N, const ProjJob* jobs, const int64_t* start, int njobs, int64_t blocks,
+                           hipStream_t st) {
+  if (njobs <= 0 || blocks <= 0) return 0;
+  const int nt = (N + 15) / 16;
+  dim3 grid((unsigned)blocks), block(256);
+  switch (nt) {
+#define CASE(K) \
+  case K: hipLaunchKernelGGL(gemm_proj_batch_f64<K>, grid, block, 0, st, jobs, start, njobs); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_quadform_batch(const ProjJob* jobs, const int64_t* start, int njobs, int64_t blocks, hipStream_t st) {
+  if (njobs <= 0 || blocks <= 0) return 0;
+  hipLaunchKernelGGL(quadform_batch_f64, dim3((unsigned)blocks), dim3(256), 0, st, jobs, start, njobs);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -215,8 +215,9 @@ __device__ __forceinline__ T max_step(const T (&x)[S], const T (&dx)[S], const b
   return gmin<G>(m);
 }
 
+// One workgroup's pixels: block blk of the cube described by prm.
 template <typename T, int NC, int G, int MODE>
-__global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
+__device__ __forceinline__ void ipm_body(const IpmParams& prm, int64_t blk) {
   using PX = Px<T, NC, G>;
   constexpr int S = PX::S;
   constexpr int GPW = 64 / G;
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = lane % G, grp = lane / G;
   const int gib = wave * GPW + grp;
-  const int64_t p = (int64_t)blockIdx.x * GPB + gib;
+  const int64_t p = blk * GPB + gib;
   const bool inrange = p < prm.P;
   const int n = prm.n;
 
@@ -582,19 +583,41 @@ __global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
 // of ipm_shapes.def (LM_T, LM_NC, LM_G defined), so shapes build in parallel;
 // ipm_dispatch.cpp picks the shape for a library at run time.
 // ---------------------------------------------------------------------------
-template <typename T, int NC, int G>
-static int launch_shape(const IpmParams& p, int mode, hipStream_t st) {
+template <typename T, int NC, int G, int MODE>
+__global__ __launch_bounds__(256) void ipm_kernel(IpmParams prm) {
+  ipm_body<T, NC, G, MODE>(prm, blockIdx.x);
+}
+
+// Several cubes in one launch (one job per cube, blocks assigned by start).
+template <typename T, int NC, int G, int MODE>
+__global__ __launch_bounds__(256) void ipm_batch_kernel(const IpmParams* __restrict__ jobs,
+                                                        const int64_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const IpmParams prm = uniform_copy(jobs + j);
+  ipm_body<T, NC, G, MODE>(prm, (int64_t)blockIdx.x - start[j]);
+}
+
+template <typename T, int NC, int G, int MODE>
+static void launch_mode(const IpmParams& p, const IpmBatch* b, hipStream_t st) {
   constexpr int GPB = 4 * (64 / G);
-  const int64_t blocks = (p.P + GPB - 1) / GPB;
-  const dim3 grid((unsigned)blocks), block(256);
+  if (b)
+    hipLaunchKernelGGL((ipm_batch_kernel<T, NC, G, MODE>), dim3((unsigned)b->blocks), dim3(256), 0, st, b->jobs,
+                       b->start, b->njobs);
+  else
+    hipLaunchKernelGGL((ipm_kernel<T, NC, G, MODE>), dim3((unsigned)((p.P + GPB - 1) / GPB)), dim3(256), 0, st, p);
+}
+
+// b == nullptr: one cube described by p; else the jobs of b.
+template <typename T, int NC, int G>
+static int launch_shape(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
     if (mode != kStage1) return -5;
-    hipLaunchKernelGGL((ipm_kernel<T, NC, G, kStage1>), grid, block, 0, st, p);
+    launch_mode<T, NC, G, kStage1>(p, b, st);
   } else {
     if (mode == kFull)
-      hipLaunchKernelGGL((ipm_kernel<T, NC, G, kFull>), grid, block, 0, st, p);
+      launch_mode<T, NC, G, kFull>(p, b, st);
     else if (mode == kStage2)
-      hipLaunchKernelGGL((ipm_kernel<T, NC, G, kStage2>), grid, block, 0, st, p);
+      launch_mode<T, NC, G, kStage2>(p, b, st);
     else
       return -5;
   }
@@ -604,8 +627,8 @@ static int launch_shape(const IpmParams& p, int mode, hipStream_t st) {
 #if defined(LM_T) && defined(LM_NC) && defined(LM_G)
 #define LM_ENTRY2(t, nc, g) ipm_entry_##t##_##nc##_##g
 #define LM_ENTRY(t, nc, g) LM_ENTRY2(t, nc, g)
-int LM_ENTRY(LM_T, LM_NC, LM_G)(const IpmParams& p, int mode, hipStream_t st) {
-  return launch_shape<LM_T, LM_NC, LM_G>(p, mode, st);
+int LM_ENTRY(LM_T, LM_NC, LM_G)(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
+  return launch_shape<LM_T, LM_NC, LM_G>(p, b, mode, st);
 }
 #endif
 

@@ -6,8 +6,9 @@
 
 namespace lm {
 
-#define LM_SHAPE(t, nc, g) int ipm_entry_##t##_##nc##_##g(const IpmParams& p, int mode, hipStream_t st);
-#define LM_TILE(t) int ipm_tile_entry_##t(const IpmParams& p, int mode, hipStream_t st);
+#define LM_SHAPE(t, nc, g) \
+  int ipm_entry_##t##_##nc##_##g(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
+#define LM_TILE(t) int ipm_tile_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
@@ -43,25 +44,63 @@ static bool use_tile(int nc) {
   return have;
 }
 
-int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st) {
-  if (p.P <= 0) return 0;
-  const int nc = ipm_shape_nc(p.n);
+// lanes per pixel of the lane-group shape for (nc, precision), or -1
+static int group_lanes(int nc, bool fp32) {
+#define LM_SHAPE(t, nc_, g) \
+  if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return g;
+#define LM_TILE(t)
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+  return -1;
+}
+
+int ipm_kernel_class(int n, bool fp32) {
+  const int nc = ipm_shape_nc(n);
+  if (nc < 0) return -1;
+  if (!fp32 && use_tile(nc)) return 1000 + nc;
+  return group_lanes(nc, fp32) > 0 ? (fp32 ? 3000 : 2000) + nc : -1;
+}
+
+int ipm_pixels_per_block(int n, bool fp32) {
+  const int nc = ipm_shape_nc(n);
+  if (nc < 0) return -1;
+  if (!fp32 && use_tile(nc)) return 16;  // four pixels per wavefront, four wavefronts
+  const int g = group_lanes(nc, fp32);
+  return g > 0 ? 4 * (64 / g) : -1;
+}
+
+static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool fp32, hipStream_t st) {
+  const int nc = ipm_shape_nc(n);
   if (nc < 0) return -5;
   if (!fp32 && use_tile(nc)) {
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t) \
-    if (4 * t == nc) return ipm_tile_entry_##t(p, mode, st);
+    if (4 * t == nc) return ipm_tile_entry_##t(p, b, mode, st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
   }
 #define LM_SHAPE(t, nc_, g)                                              \
-  if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return ipm_entry_##t##_##nc_##_##g(p, mode, st);
+  if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return ipm_entry_##t##_##nc_##_##g(p, b, mode, st);
 #define LM_TILE(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
   return -5;
+}
+
+int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st) {
+  if (p.P <= 0) return 0;
+  return dispatch(p.n, p, nullptr, mode, fp32, st);
+}
+
+int launch_ipm_batch(int n, int constraint, const IpmBatch& b, int mode, bool fp32, hipStream_t st) {
+  if (b.njobs <= 0 || b.blocks <= 0) return 0;
+  IpmParams p{};
+  p.n = n;
+  p.constraint = constraint;
+  return dispatch(n, p, &b, mode, fp32, st);
 }
 
 }  // namespace lm

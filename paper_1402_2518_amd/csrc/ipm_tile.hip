@@ -239,8 +239,9 @@ struct Tile {
   }
 };
 
+// One workgroup's 16 pixels: workgroup wg of the cube described by prm.
 template <int T, int MODE, int CONS>
-__global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
+__device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) {
   using TL = Tile<T>;
   constexpr int NP = TL::NP;
   constexpr int C = TL::C;
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int blk = (lane >> 2) & 3, x = lane >> 4, z = lane & 3;
   const int pib = wave * 4 + blk;
-  const int64_t p = (int64_t)blockIdx.x * 16 + pib;
+  const int64_t p = wg * 16 + pib;
   const bool inrange = p < prm.P;
   const int n = prm.n;
 
@@ -631,25 +632,48 @@ __global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
   }
 }
 
+template <int T, int MODE, int CONS>
+__global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
+  ipm_tile_body<T, MODE, CONS>(prm, blockIdx.x);
+}
+
+// Several cubes in one launch (one job per cube, blocks assigned by start).
+template <int T, int MODE, int CONS>
+__global__ __launch_bounds__(256, 2) void ipm_tile_batch_kernel(const IpmParams* __restrict__ jobs,
+                                                                 const int64_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const IpmParams prm = uniform_copy(jobs + j);
+  ipm_tile_body<T, MODE, CONS>(prm, (int64_t)blockIdx.x - start[j]);
+}
+
+template <int T, int MODE, int CONS>
+static void launch_tile_m(const IpmParams& p, const IpmBatch* b, hipStream_t st) {
+  if (b)
+    hipLaunchKernelGGL((ipm_tile_batch_kernel<T, MODE, CONS>), dim3((unsigned)b->blocks), dim3(256), 0, st, b->jobs,
+                       b->start, b->njobs);
+  else
+    hipLaunchKernelGGL((ipm_tile_kernel<T, MODE, CONS>), dim3((unsigned)((p.P + 15) / 16)), dim3(256), 0, st, p);
+}
+
 template <int T, int CONS>
-static int launch_tile_c(const IpmParams& p, int mode, hipStream_t st) {
-  const int64_t blocks = (p.P + 15) / 16;
-  const dim3 grid((unsigned)blocks), block(256);
+static int launch_tile_c(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
   if (mode == kFull)
-    hipLaunchKernelGGL((ipm_tile_kernel<T, kFull, CONS>), grid, block, 0, st, p);
+    launch_tile_m<T, kFull, CONS>(p, b, st);
   else if (mode == kStage2)
-    hipLaunchKernelGGL((ipm_tile_kernel<T, kStage2, CONS>), grid, block, 0, st, p);
+    launch_tile_m<T, kStage2, CONS>(p, b, st);
   else
     return -5;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// b == nullptr: one cube described by p; else the jobs of b (p only gives
+// the constraint option, shared by every job).
 template <int T>
-static int launch_tile(const IpmParams& p, int mode, hipStream_t st) {
+static int launch_tile(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
   switch (p.constraint) {
-    case kSto: return launch_tile_c<T, kSto>(p, mode, st);
-    case kSlo: return launch_tile_c<T, kSlo>(p, mode, st);
-    case kPos: return launch_tile_c<T, kPos>(p, mode, st);
+    case kSto: return launch_tile_c<T, kSto>(p, b, mode, st);
+    case kSlo: return launch_tile_c<T, kSlo>(p, b, mode, st);
+    case kPos: return launch_tile_c<T, kPos>(p, b, mode, st);
   }
   return -1;
 }
@@ -657,7 +681,9 @@ static int launch_tile(const IpmParams& p, int mode, hipStream_t st) {
 #if defined(LM_TILE_T)
 #define LM_TENTRY2(t) ipm_tile_entry_##t
 #define LM_TENTRY(t) LM_TENTRY2(t)
-int LM_TENTRY(LM_TILE_T)(const IpmParams& p, int mode, hipStream_t st) { return launch_tile<LM_TILE_T>(p, mode, st); }
+int LM_TENTRY(LM_TILE_T)(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
+  return launch_tile<LM_TILE_T>(p, b, mode, st);
+}
 #endif
 
 }  // namespace lm

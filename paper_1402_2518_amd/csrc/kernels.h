@@ -58,17 +58,79 @@ struct IpmParams {
   double* dcorner;      // P or NULL: corner of the covariance's bordered matrix (-inf: no border)
 };
 
-// ipm.hip: picks the compiled (NC, G) shape for n and precision.
-int ipm_shape_nc(int n);                  // padded size NC used for a library of size n
+// Jobs of a batched interior-point launch: one IpmParams per cube, every
+// cube of one launch with the same compiled shape and options.
+struct IpmBatch {
+  const IpmParams* jobs;  // device, njobs
+  const int64_t* start;   // device, njobs + 1: first block of each job, then the total
+  int njobs;
+  int64_t blocks;         // total workgroups of the launch
+};
+
+// ipm_dispatch.cpp: picks the compiled shape for n and precision.
+int ipm_shape_nc(int n);                      // padded size NC used for a library of size n
+int ipm_pixels_per_block(int n, bool fp32);   // pixels of one workgroup for that shape
+int ipm_kernel_class(int n, bool fp32);       // launches of equal class can share a batch
 int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st);
+// batched: every job of b has a library with ipm_kernel_class(n, fp32) equal
+// to that of n; constraint as in IpmParams
+int launch_ipm_batch(int n, int constraint, const IpmBatch& b, int mode, bool fp32, hipStream_t st);
 
 // gemm.hip
+// One cube of a batched projection launch: bh = Y W (and c = y^T y, or
+// y^T Ci y by the quadratic-form launch when Ci is given).
+struct ProjJob {
+  const float* Y;
+  int64_t P;
+  int L;
+  const double* W;
+  int ldw;
+  int N;
+  double* B;
+  double* c;
+  const double* Ci;  // L x ldc inverse noise covariance, or NULL
+  int ldc;
+};
+int proj_pixels_per_block();  // pixels of one projection workgroup (both kernels)
+// batched: libraries of one launch share (N + 15) / 16; start: first block of
+// each job, then the total
+int launch_gemm_proj_batch(int N, const ProjJob* jobs, const int64_t* start, int njobs, int64_t blocks,
+                           hipStream_t st);
+int launch_quadform_batch(const ProjJob* jobs, const int64_t* start, int njobs, int64_t blocks, hipStream_t st);
 int launch_gemm_proj_f64(const float* Y, int64_t P, int L, const double* W, int ldw, int N,
                          double* B, double* c, hipStream_t st);
 int launch_quadform_f64(const float* Y, int64_t P, int L, const double* Ci, int ldc, double* c,
                         hipStream_t st);
 
 // cov.hip
+// One cube of a covariance pass (the arguments of launch_cov).
+struct CovJob {
+  int n;
+  int64_t P;
+  const double* Gh;
+  int ldg;
+  const double* dcov;
+  const double* corner;
+  const float* sigma;
+  double gamma;
+  const uint8_t* status;
+  int layout;
+  double* out;
+  uint8_t* big;
+};
+// Jobs of one batched covariance path.  units: workgroups of 16 pixels for
+// the first path, 64-pixel chunks for the other two; start: first unit of
+// each job, then the total.  The first path takes every job, the second the
+// jobs with n + 1 > 16, the third those with n + 1 > 32 (qcap: their largest
+// n + 1).
+struct CovBatch {
+  const CovJob* jobs;
+  const int64_t* start;
+  int njobs;
+  int64_t units;
+  int qcap;
+};
+int launch_cov_batch(const CovBatch& small, const CovBatch& mid, const CovBatch& big, hipStream_t st);
 // corner: P values (0: sum row, finite < 0: sum row with that corner, -inf:
 // no sum row); big: P bytes of workspace (pixels routed to larger paths)
 int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, const double* corner,

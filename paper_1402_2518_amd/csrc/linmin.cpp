@@ -12,7 +12,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <new>
+#include <vector>
 
 #include "../../include/linmin.h"
 #include "kernels.h"
@@ -90,6 +92,56 @@ Work plan(const linmin_lib_s* lib, int64_t P, const linmin_opts& o, bool want_co
   w.status = (o.status == nullptr) ? take(p) : (size_t)-1;
   w.total = off;
   return w;
+}
+
+// Interior-point arguments of one cube; ws is the cube's work area laid out
+// by plan(), status the per-pixel status array (caller's or in ws).
+lm::IpmParams make_ipm(const linmin_lib_s* lib, int64_t P, const float* sigma, double* out_coeffs, uint8_t* status,
+                       int32_t* iters, double* objective, const linmin_opts& o, const Work& w, char* ws,
+                       bool want_cov) {
+  auto at = [&](size_t off) -> char* { return off == (size_t)-1 ? nullptr : ws + off; };
+  lm::IpmParams prm{};
+  prm.n = lib->N;
+  prm.P = P;
+  prm.bh = (double*)at(w.bh);
+  prm.c = (double*)at(w.c);
+  prm.sigma = sigma;
+  prm.gamma = lib->gamma;
+  prm.maxit = o.maxit;
+  prm.max_polish = o.max_polish;
+  prm.constraint = o.constraint;
+  prm.tol_mu = o.tol_mu;
+  prm.tol_d = o.tol_d;
+  prm.tol_p = o.tol_p;
+  prm.eta = o.eta;
+  prm.lambda0 = o.lambda0;
+  prm.tau = o.tau;
+  prm.deg_tol = o.deg_tol;
+  prm.mu_switch = o.mu_switch;
+  prm.out_a = out_coeffs;
+  prm.status = status;
+  prm.iters = iters;
+  prm.objective = objective;
+  prm.dcov = want_cov ? (double*)at(w.dcov) : nullptr;
+  prm.dcorner = want_cov ? (double*)at(w.dcorner) : nullptr;
+  if (o.precision == LINMIN_MIXED) {
+    prm.st_a = (double*)at(w.st_a);
+    prm.st_lam = (double*)at(w.st_lam);
+    prm.st_nu = (double*)at(w.st_nu);
+    prm.st_s = (double*)at(w.st_s);
+    prm.st_it = (int32_t*)at(w.st_it);
+    prm.st_flag = (uint8_t*)at(w.st_flag);
+  }
+  prm.Gh = lib->Gh64;
+  return prm;
+}
+
+int check_opts(const linmin_opts& o) {
+  if (o.precision != LINMIN_FP64 && o.precision != LINMIN_MIXED) return LINMIN_EINVAL;
+  if (o.cov_layout < LINMIN_COV_NONE || o.cov_layout > LINMIN_COV_DIAG) return LINMIN_EINVAL;
+  if (o.maxit < 0 || o.max_polish < 0 || !(o.eta > 0.0 && o.eta < 1.0) || !(o.lambda0 > 0.0)) return LINMIN_EINVAL;
+  if (o.constraint != LINMIN_STO && o.constraint != LINMIN_SLO && o.constraint != LINMIN_POS) return LINMIN_EINVAL;
+  return LINMIN_OK;
 }
 
 }  // namespace
@@ -273,10 +325,10 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   linmin_opts o;
   if (opts) o = *opts;
   else linmin_default_opts(&o);
-  if (o.precision != LINMIN_FP64 && o.precision != LINMIN_MIXED) return LINMIN_EINVAL;
-  if (o.cov_layout < LINMIN_COV_NONE || o.cov_layout > LINMIN_COV_DIAG) return LINMIN_EINVAL;
-  if (o.maxit < 0 || o.max_polish < 0 || !(o.eta > 0.0 && o.eta < 1.0) || !(o.lambda0 > 0.0)) return LINMIN_EINVAL;
-  if (o.constraint != LINMIN_STO && o.constraint != LINMIN_SLO && o.constraint != LINMIN_POS) return LINMIN_EINVAL;
+  {
+    const int rc0 = check_opts(o);
+    if (rc0 != LINMIN_OK) return rc0;
+  }
   if (P == 0) return LINMIN_OK;
   if (!cube || !out_coeffs) return LINMIN_EINVAL;
   const bool want_cov = out_cov != nullptr && o.cov_layout != LINMIN_COV_NONE;
@@ -305,37 +357,8 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   if (rc == LINMIN_OK && lib->Ci) rc = from_launch(lm::launch_quadform_f64(cube, P, lib->L, lib->Ci, lib->L, c, st));
   if (rc == LINMIN_OK) rc = mark(1);
   if (rc == LINMIN_OK) {
-    lm::IpmParams prm{};
-    prm.n = lib->N;
-    prm.P = P;
-    prm.bh = bh;
-    prm.c = c;
-    prm.sigma = sigma;
-    prm.gamma = lib->gamma;
-    prm.maxit = o.maxit;
-    prm.max_polish = o.max_polish;
-    prm.constraint = o.constraint;
-    prm.tol_mu = o.tol_mu;
-    prm.tol_d = o.tol_d;
-    prm.tol_p = o.tol_p;
-    prm.eta = o.eta;
-    prm.lambda0 = o.lambda0;
-    prm.tau = o.tau;
-    prm.deg_tol = o.deg_tol;
-    prm.mu_switch = o.mu_switch;
-    prm.out_a = out_coeffs;
-    prm.status = status;
-    prm.iters = o.iters;
-    prm.objective = o.objective;
-    prm.dcov = want_cov ? (double*)at(w.dcov) : nullptr;
-    prm.dcorner = want_cov ? (double*)at(w.dcorner) : nullptr;
+    lm::IpmParams prm = make_ipm(lib, P, sigma, out_coeffs, status, o.iters, o.objective, o, w, ws, want_cov);
     if (o.precision == LINMIN_MIXED) {
-      prm.st_a = (double*)at(w.st_a);
-      prm.st_lam = (double*)at(w.st_lam);
-      prm.st_nu = (double*)at(w.st_nu);
-      prm.st_s = (double*)at(w.st_s);
-      prm.st_it = (int32_t*)at(w.st_it);
-      prm.st_flag = (uint8_t*)at(w.st_flag);
       prm.Gh = lib->Gh32;
       rc = from_launch(lm::launch_ipm(prm, lm::kStage1, true, st));
       if (rc == LINMIN_OK) {
@@ -354,6 +377,252 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   if (rc == LINMIN_OK) rc = mark(3);
   if (hipFreeAsync(ws, st) != hipSuccess && rc == LINMIN_OK) rc = LINMIN_EHIP;
   return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many cubes, possibly of different libraries, in a few launches.
+// The plan groups the cubes by compiled kernel (projection column blocks,
+// interior-point shape) and uploads one job table per launch; a run only
+// enqueues kernels.
+// ---------------------------------------------------------------------------
+struct linmin_batch_s {
+  int dev = -1;
+  linmin_opts o{};
+  char* ws = nullptr;   // device: the cubes' work areas
+  char* tab = nullptr;  // device: job tables and their block prefixes
+  size_t ws_bytes = 0, tab_bytes = 0;
+  struct Proj {
+    int N;
+    const lm::ProjJob* jobs;
+    const int64_t* start;
+    int njobs;
+    int64_t blocks;
+  };
+  std::vector<Proj> proj;
+  Proj quad{0, nullptr, nullptr, 0, 0};
+  struct Ipm {
+    int n, mode;
+    bool fp32;
+    lm::IpmBatch b;
+  };
+  std::vector<Ipm> ipm;  // in launch order
+  lm::CovBatch cov[3]{};
+};
+
+namespace {
+
+// host image of the job tables: arrays appended at 256-byte boundaries
+struct Image {
+  std::vector<char> bytes;
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    const size_t at = align256(bytes.size());
+    bytes.resize(at + sizeof(T) * v.size());
+    if (!v.empty()) memcpy(bytes.data() + at, v.data(), sizeof(T) * v.size());
+    return at;
+  }
+};
+
+// a group's jobs and its prefix of work units (njobs + 1 values)
+template <typename J>
+struct Group {
+  std::vector<J> jobs;
+  std::vector<int64_t> start{0};
+  size_t jobs_at = 0, start_at = 0;
+  void add(const J& j, int64_t units) {
+    jobs.push_back(j);
+    start.push_back(start.back() + units);
+  }
+  void place(Image& im) {
+    jobs_at = im.put(jobs);
+    start_at = im.put(start);
+  }
+  int64_t units() const { return start.back(); }
+};
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+extern "C" {
+
+int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* opts, linmin_batch* out) {
+  if (!out || n_jobs < 0 || (n_jobs > 0 && !jobs)) return LINMIN_EINVAL;
+  *out = nullptr;
+  linmin_opts o;
+  if (opts) o = *opts;
+  else linmin_default_opts(&o);
+  int rc = check_opts(o);
+  if (rc != LINMIN_OK) return rc;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LINMIN_EHIP;
+  for (int j = 0; j < n_jobs; ++j) {
+    const linmin_job& J = jobs[j];
+    if (!J.lib || J.P < 0 || J.lib->dev != dev) return LINMIN_EINVAL;
+    if (J.P > 0 && (!J.cube || !J.out_coeffs)) return LINMIN_EINVAL;
+    if (lm::ipm_kernel_class(J.lib->N, false) < 0 || lm::ipm_kernel_class(J.lib->N, true) < 0)
+      return LINMIN_EUNSUPPORTED;
+  }
+  const bool mixed = o.precision == LINMIN_MIXED;
+  const bool any_cov = o.cov_layout != LINMIN_COV_NONE;
+
+  // work areas, one after the other
+  std::vector<Work> work(n_jobs);
+  std::vector<size_t> base(n_jobs, 0);
+  size_t total = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (jobs[j].P == 0) continue;
+    linmin_opts oj = o;
+    oj.status = jobs[j].status;
+    work[j] = plan(jobs[j].lib, jobs[j].P, oj, any_cov && jobs[j].out_cov);
+    base[j] = total;
+    total += align256(work[j].total);
+  }
+  linmin_batch b = new (std::nothrow) linmin_batch_s;
+  if (!b) return LINMIN_ENOMEM;
+  b->dev = dev;
+  b->o = o;
+  b->ws_bytes = total;
+  if (total && hipMalloc((void**)&b->ws, total) != hipSuccess) {
+    delete b;
+    return LINMIN_ENOMEM;
+  }
+
+  // job tables
+  std::map<int, Group<lm::ProjJob>> proj;  // by column blocks
+  Group<lm::ProjJob> quad;
+  std::map<int, Group<lm::IpmParams>> ipm1, ipm2;  // by kernel class: FP64 (or stage 2), FP32 stage 1
+  std::map<int, int> class_n1, class_n2;           // a library size of each class
+  Group<lm::CovJob> cov[3];
+  int qcap = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const linmin_job& J = jobs[j];
+    if (J.P == 0) continue;
+    const linmin_lib_s* lib = J.lib;
+    const Work& w = work[j];
+    char* ws = b->ws + base[j];
+    auto at = [&](size_t off) -> char* { return off == (size_t)-1 ? nullptr : ws + off; };
+    const bool want_cov = any_cov && J.out_cov;
+    uint8_t* status = J.status ? J.status : (uint8_t*)at(w.status);
+    const int64_t P = J.P;
+
+    lm::ProjJob pj{J.cube, P, lib->L, lib->Wh, lib->ldw, lib->N, (double*)at(w.bh), (double*)at(w.c), lib->Ci,
+                   lib->L};
+    proj[(lib->N + 15) / 16].add(pj, cdiv(P, lm::proj_pixels_per_block()));
+    if (lib->Ci) quad.add(pj, cdiv(P, lm::proj_pixels_per_block()));
+
+    lm::IpmParams prm = make_ipm(lib, P, J.sigma, J.out_coeffs, status, J.iters, J.objective, o, w, ws, want_cov);
+    const int k2 = lm::ipm_kernel_class(lib->N, false);
+    prm.Gh = lib->Gh64;
+    ipm2[k2].add(prm, cdiv(P, lm::ipm_pixels_per_block(lib->N, false)));
+    class_n2[k2] = lib->N;
+    if (mixed) {
+      const int k1 = lm::ipm_kernel_class(lib->N, true);
+      prm.Gh = lib->Gh32;
+      ipm1[k1].add(prm, cdiv(P, lm::ipm_pixels_per_block(lib->N, true)));
+      class_n1[k1] = lib->N;
+    }
+    if (want_cov) {
+      const lm::CovJob cj{lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), (double*)at(w.dcorner), J.sigma,
+                          lib->gamma, status, o.cov_layout, J.out_cov, (uint8_t*)at(w.big)};
+      cov[0].add(cj, cdiv(P, 16));
+      if (lib->N + 1 > 16) cov[1].add(cj, cdiv(P, 64));
+      if (lib->N + 1 > 32) {
+        cov[2].add(cj, cdiv(P, 64));
+        if (lib->N + 1 > qcap) qcap = lib->N + 1;
+      }
+    }
+  }
+  Image im;
+  for (auto& kv : proj) kv.second.place(im);
+  quad.place(im);
+  for (auto& kv : ipm1) kv.second.place(im);
+  for (auto& kv : ipm2) kv.second.place(im);
+  for (auto& g : cov) g.place(im);
+  b->tab_bytes = im.bytes.size();
+  if (b->tab_bytes) {
+    if (hipMalloc((void**)&b->tab, b->tab_bytes) != hipSuccess) {
+      linmin_batch_destroy(b);
+      return LINMIN_ENOMEM;
+    }
+    if (hipMemcpy(b->tab, im.bytes.data(), b->tab_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      linmin_batch_destroy(b);
+      return LINMIN_EHIP;
+    }
+  }
+  char* t = b->tab;
+  for (auto& kv : proj) {
+    const auto& g = kv.second;
+    b->proj.push_back({g.jobs.front().N, (const lm::ProjJob*)(t + g.jobs_at), (const int64_t*)(t + g.start_at),
+                       (int)g.jobs.size(), g.units()});
+  }
+  if (!quad.jobs.empty())
+    b->quad = {0, (const lm::ProjJob*)(t + quad.jobs_at), (const int64_t*)(t + quad.start_at), (int)quad.jobs.size(),
+               quad.units()};
+  auto add_ipm = [&](std::map<int, Group<lm::IpmParams>>& m, std::map<int, int>& nmap, int mode, bool fp32) {
+    for (auto& kv : m) {
+      const auto& g = kv.second;
+      linmin_batch_s::Ipm e{nmap[kv.first], mode, fp32,
+                            {(const lm::IpmParams*)(t + g.jobs_at), (const int64_t*)(t + g.start_at),
+                             (int)g.jobs.size(), g.units()}};
+      b->ipm.push_back(e);
+    }
+  };
+  if (mixed) {
+    add_ipm(ipm1, class_n1, lm::kStage1, true);
+    add_ipm(ipm2, class_n2, lm::kStage2, false);
+  } else {
+    add_ipm(ipm2, class_n2, lm::kFull, false);
+  }
+  for (int k = 0; k < 3; ++k) {
+    const auto& g = cov[k];
+    if (!g.jobs.empty())
+      b->cov[k] = {(const lm::CovJob*)(t + g.jobs_at), (const int64_t*)(t + g.start_at), (int)g.jobs.size(), g.units(),
+                   qcap};
+  }
+  *out = b;
+  return LINMIN_OK;
+}
+
+int linmin_batch_run(linmin_batch b, void* stream) {
+  if (!b) return LINMIN_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LINMIN_EHIP;
+  if (dev != b->dev) return LINMIN_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(b->o.stage_events);
+  auto mark = [&](int i) {
+    if (ev && hipEventRecord(ev[i], st) != hipSuccess) return LINMIN_EHIP;
+    return LINMIN_OK;
+  };
+  int rc = mark(0);
+  for (size_t i = 0; rc == LINMIN_OK && i < b->proj.size(); ++i) {
+    const auto& g = b->proj[i];
+    rc = from_launch(lm::launch_gemm_proj_batch(g.N, g.jobs, g.start, g.njobs, g.blocks, st));
+  }
+  if (rc == LINMIN_OK && b->quad.njobs)
+    rc = from_launch(lm::launch_quadform_batch(b->quad.jobs, b->quad.start, b->quad.njobs, b->quad.blocks, st));
+  if (rc == LINMIN_OK) rc = mark(1);
+  for (size_t i = 0; rc == LINMIN_OK && i < b->ipm.size(); ++i) {
+    const auto& g = b->ipm[i];
+    rc = from_launch(lm::launch_ipm_batch(g.n, b->o.constraint, g.b, g.mode, g.fp32, st));
+  }
+  if (rc == LINMIN_OK) rc = mark(2);
+  if (rc == LINMIN_OK) rc = from_launch(lm::launch_cov_batch(b->cov[0], b->cov[1], b->cov[2], st));
+  if (rc == LINMIN_OK) rc = mark(3);
+  return rc;
+}
+
+size_t linmin_batch_device_bytes(linmin_batch b) { return b ? b->ws_bytes + b->tab_bytes : 0; }
+
+int linmin_batch_destroy(linmin_batch b) {
+  if (!b) return LINMIN_EINVAL;
+  (void)hipFree(b->ws);
+  (void)hipFree(b->tab);
+  delete b;
+  return LINMIN_OK;
 }
 
 }  // extern "C"

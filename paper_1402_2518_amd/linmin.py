@@ -24,7 +24,8 @@ N_MAX = 128
 
 EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linmin_workspace_bytes",
            "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror",
-           "linmin_extra_spectra")
+           "linmin_extra_spectra", "linmin_batch_create", "linmin_batch_run", "linmin_batch_device_bytes",
+           "linmin_batch_destroy")
 
 
 class Opts(ctypes.Structure):
@@ -35,6 +36,12 @@ class Opts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("deg_tol", ctypes.c_double), ("mu_switch", ctypes.c_double),
                 ("status", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("objective", ctypes.c_void_p),
                 ("stage_events", ctypes.c_void_p)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("lib", ctypes.c_void_p), ("cube", ctypes.c_void_p), ("P", ctypes.c_int64),
+                ("sigma", ctypes.c_void_p), ("out_coeffs", ctypes.c_void_p), ("out_cov", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("objective", ctypes.c_void_p)]
 
 
 class LinminError(RuntimeError):
@@ -71,6 +78,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.linmin_destroy_library.restype = ctypes.c_int
         lib.linmin_extra_spectra.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp]
         lib.linmin_extra_spectra.restype = ctypes.c_int
+        lib.linmin_batch_create.argtypes = [ctypes.POINTER(Job), ctypes.c_int, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        lib.linmin_batch_create.restype = ctypes.c_int
+        lib.linmin_batch_run.argtypes = [vp, vp]
+        lib.linmin_batch_run.restype = ctypes.c_int
+        lib.linmin_batch_device_bytes.argtypes = [vp]
+        lib.linmin_batch_device_bytes.restype = ctypes.c_size_t
+        lib.linmin_batch_destroy.argtypes = [vp]
+        lib.linmin_batch_destroy.restype = ctypes.c_int
         lib.linmin_strerror.argtypes = [ctypes.c_int]
         lib.linmin_strerror.restype = ctypes.c_char_p
         _lib = lib
@@ -233,3 +248,72 @@ class Library:
         obj = torch.empty(P, dtype=torch.float64, device=dev)
         self.unmix_into(cube, sigma, a, cv, st, it, obj, precision=precision, cov=cov, stream=stream, **opts)
         return {"a": a, "cov": cv, "status": st, "iters": it, "objective": obj}
+
+
+def _cov_shape(cov, P, N):
+    return {None: None, "none": None, "full": (P, N, N), "packed": (P, N * (N + 1) // 2), "diag": (P, N)}[cov]
+
+
+class Batch:
+    """Many cubes, each with its own :class:`Library`, planned once
+    (``linmin_batch_create``) and unmixed by :meth:`run` in a few fused
+    launches.  ``items``: a sequence of ``(library, cube, sigma)`` with cube a
+    contiguous P x L float32 device tensor and sigma a P float32 device tensor
+    or None.  Output tensors are allocated here and reused by every run:
+    ``results[i]`` holds ``a``, ``cov``, ``status``, ``iters``, ``objective``
+    of item i.
+    """
+
+    def __init__(self, items, precision: str = "fp64", cov: str | None = "full", **opts):
+        import torch
+        if isinstance(opts.get("constraint"), str):
+            opts["constraint"] = _CONS[opts["constraint"]]
+        self._opts = default_opts(precision=_PREC[precision], cov_layout=_COV[cov], **opts)
+        self.items = list(items)
+        self.results = []
+        jobs = (Job * max(1, len(self.items)))()
+        for i, (lib, cube, sigma) in enumerate(self.items):
+            if cube.dtype != torch.float32 or not cube.is_contiguous() or cube.dim() != 2 or cube.shape[1] != lib.L:
+                raise ValueError(f"item {i}: cube must be a contiguous P x {lib.L} float32 tensor")
+            P, N, dev = cube.shape[0], lib.N, cube.device
+            if sigma is not None and (sigma.dtype != torch.float32 or sigma.numel() != P or not sigma.is_contiguous()):
+                raise ValueError(f"item {i}: sigma must be a contiguous float32 tensor of P values")
+            shp = _cov_shape(cov, P, N)
+            r = {"a": torch.empty((P, N), dtype=torch.float64, device=dev),
+                 "cov": None if shp is None else torch.empty(shp, dtype=torch.float64, device=dev),
+                 "status": torch.empty(P, dtype=torch.uint8, device=dev),
+                 "iters": torch.empty(P, dtype=torch.int32, device=dev),
+                 "objective": torch.empty(P, dtype=torch.float64, device=dev)}
+            self.results.append(r)
+            jobs[i] = Job(lib._h.value, cube.data_ptr(), P, None if sigma is None else sigma.data_ptr(),
+                          r["a"].data_ptr(), None if r["cov"] is None else r["cov"].data_ptr(),
+                          r["status"].data_ptr(), r["iters"].data_ptr(), r["objective"].data_ptr())
+        h = ctypes.c_void_p()
+        rc = load().linmin_batch_create(jobs, len(self.items), ctypes.byref(self._opts), ctypes.byref(h))
+        if rc != OK:
+            raise LinminError(rc, "linmin_batch_create")
+        self._h = h
+
+    def device_bytes(self) -> int:
+        return int(load().linmin_batch_device_bytes(self._h))
+
+    def run(self, stream=None):
+        """Enqueue every item on ``stream`` (default: torch's current stream)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        rc = load().linmin_batch_run(self._h, ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise LinminError(rc, "linmin_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().linmin_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

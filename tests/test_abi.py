@@ -67,3 +67,18 @@ def test_strerror_and_defaults_without_gpu():
     assert lib.linmin_create_library(None, 3, 2, None, ctypes.byref(h)) == linmin.EINVAL
     assert lib.linmin_unmix(None, None, 0, None, None, None, None, None) == linmin.EINVAL
     assert lib.linmin_destroy_library(None) == linmin.EINVAL
+    # batches: misuse is reported before any device work
+    assert lib.linmin_batch_create(None, 0, None, None) == linmin.EINVAL
+    assert lib.linmin_batch_create(None, -1, None, ctypes.byref(h)) == linmin.EINVAL
+    assert lib.linmin_batch_create(None, 2, None, ctypes.byref(h)) == linmin.EINVAL
+    bad = linmin.default_opts(precision=7)
+    assert lib.linmin_batch_create(None, 0, ctypes.byref(bad), ctypes.byref(h)) == linmin.EINVAL
+    assert lib.linmin_batch_run(None, None) == linmin.EINVAL
+    assert lib.linmin_batch_destroy(None) == linmin.EINVAL
+    assert lib.linmin_batch_device_bytes(None) == 0
+
+
+def test_job_struct_layout():
+    # linmin_job: library handle, cube, P, sigma, then five output pointers
+    assert ctypes.sizeof(linmin.Job) == 9 * 8
+    assert linmin.Job.P.offset == 16
