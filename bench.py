@@ -55,6 +55,81 @@ def ipm_flops_per_iteration(n: int) -> float:
     return n ** 3 / 3.0 + 7.0 * n ** 2 + 30.0 * n
 
 
+def batch_leg(args, dev, stream):
+    """Many cubes, each with its own library, in one planned batch: fused
+    launches against the same cubes unmixed by sequential single calls."""
+    import torch
+    import oracle
+    from paper_1402_2518_amd import linmin, synth
+
+    ws = synth.batch_workloads(args.batch_cubes)
+    t0 = time.perf_counter()
+    libs, items, S_host = [], [], []
+    for w in ws:
+        S = synth.make_library(w)
+        lib = linmin.Library(S)
+        X, s = synth.make_cube_device(w, S, dev)
+        libs.append(lib)
+        items.append((lib, X, s))
+        S_host.append(S)
+    torch.cuda.synchronize()
+    P_tot = sum(w.P for w in ws)
+    print(f"# batch: {len(ws)} cubes, {P_tot} pixels, built in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    out = {"cubes": len(ws), "pixels": P_tot, "cov_layout": "diag", "runs": args.batch_runs,
+           "workload": "200 cubes, N in {16,24,36,48,64,96} and L in {128,240,438} per cube, P log-uniform "
+                       "in [1e3, 2e5], 4 extras, 1-4 active minerals, sigma~U[0.002,0.01]",
+           "pixels_by_N": {str(n): sum(w.P for w in ws if w.N == n) for n in synth.BATCH_N}}
+    for prec in ("fp64", "mixed"):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        b = linmin.Batch(items, precision=prec, cov="diag", events=evs)
+
+        def sequential():
+            for (lib, X, s), r in zip(items, b.results):
+                lib.unmix_into(X, s, r["a"], r["cov"], r["status"], r["iters"], r["objective"],
+                               precision=prec, cov="diag", stream=stream)
+
+        with torch.cuda.stream(stream):
+            b.run(stream)
+            torch.cuda.synchronize()
+            ref = [(r["a"].clone(), r["cov"].clone(), r["status"].clone()) for r in b.results]
+            t1 = time.perf_counter()
+            for _ in range(args.batch_runs):
+                b.run(stream)
+            torch.cuda.synchronize()
+            wall_b = (time.perf_counter() - t1) / args.batch_runs
+            stages = [evs[0].elapsed_time(evs[1]), evs[1].elapsed_time(evs[2]), evs[2].elapsed_time(evs[3])]
+            sequential()
+            torch.cuda.synchronize()
+            same = all(torch.equal(r["a"], a) and torch.equal(r["cov"].nan_to_num(3.5), c.nan_to_num(3.5))
+                       and torch.equal(r["status"], st) for r, (a, c, st) in zip(b.results, ref))
+            t1 = time.perf_counter()
+            for _ in range(args.batch_runs):
+                sequential()
+            torch.cuda.synchronize()
+            wall_s = (time.perf_counter() - t1) / args.batch_runs
+        # oracle on the first pixels of one cube of every library size
+        err = 0.0
+        for n in synth.BATCH_N:
+            i = next(k for k, w in enumerate(ws) if w.N == n)
+            X8, s8 = items[i][1][:8].cpu().numpy(), items[i][2][:8].cpu().numpy()
+            r = oracle.unmix(S_host[i], X8, s8, cov=False)
+            err = max(err, float(np.abs(ref[i][0][:8].cpu().numpy() - r["a"]).max()))
+        stat = torch.cat([st for _, _, st in ref]).cpu().numpy()
+        out[prec] = {"pixels_per_s": P_tot / wall_b, "ms_per_run": wall_b * 1e3,
+                     "stages_ms": {"projection": stages[0], "ipm": stages[1], "covariance": stages[2]},
+                     "sequential_pixels_per_s": P_tot / wall_s, "sequential_ms_per_run": wall_s * 1e3,
+                     "speedup_vs_sequential": wall_s / wall_b, "identical_to_single_calls": bool(same),
+                     "max_abs_coeff_err_vs_oracle_sample": err,
+                     "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stat, return_counts=True))},
+                     "device_bytes": b.device_bytes()}
+        print(f"# batch {prec}: {out[prec]}", file=sys.stderr, flush=True)
+        b.close()
+    for lib in libs:
+        lib.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +141,9 @@ def main():
                     help="sequential whole-cube calls behind the p50/p99 latency")
     ap.add_argument("--variants", type=int, default=5,
                     help="timed calls for each covariance layout / shard-size variant (0 = skip)")
+    ap.add_argument("--batch-cubes", type=int, default=200,
+                    help="cubes in the many-cube batch leg (0 = skip)")
+    ap.add_argument("--batch-runs", type=int, default=2, help="timed runs of the batch leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -199,6 +277,11 @@ def main():
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stat64, return_counts=True))},
         "roofline": roof,
     }
+
+    if args.batch_cubes > 0:
+        del out_cov
+        torch.cuda.empty_cache()
+        result["batch"] = batch_leg(args, dev, stream)
 
     if not args.no_cpu:
         oracle.build(force=False)

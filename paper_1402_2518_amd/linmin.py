@@ -264,11 +264,21 @@ class Batch:
     of item i.
     """
 
-    def __init__(self, items, precision: str = "fp64", cov: str | None = "full", **opts):
+    def __init__(self, items, precision: str = "fp64", cov: str | None = "full", events=None, **opts):
         import torch
         if isinstance(opts.get("constraint"), str):
             opts["constraint"] = _CONS[opts["constraint"]]
         self._opts = default_opts(precision=_PREC[precision], cov_layout=_COV[cov], **opts)
+        self._ev = None
+        if events is not None:
+            # four timing events recorded by every run: before the projections,
+            # the solve, the covariance, and after
+            if len(events) != 4:
+                raise ValueError("events must hold 4 timing events")
+            for e in events:
+                e.record()  # makes sure the underlying HIP event exists
+            self._ev = (ctypes.c_void_p * 4)(*[ctypes.c_void_p(e.cuda_event) for e in events])
+            self._opts.stage_events = ctypes.cast(self._ev, ctypes.c_void_p)
         self.items = list(items)
         self.results = []
         jobs = (Job * max(1, len(self.items)))()

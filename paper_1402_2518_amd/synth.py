@@ -35,6 +35,7 @@ and 12 are a library builder of the product, not an input recipe.
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 
@@ -162,6 +163,60 @@ def make_cube(w: Workload | str, S: np.ndarray | None = None, p0: int = 0,
         if with_truth:
             A[lo - p0:hi - p0] = ca[lo - c * CHUNK:hi - c * CHUNK]
     return (X, sig, A) if with_truth else (X, sig)
+
+
+def make_cube_device(w: Workload, S: np.ndarray, device, chunk: int = 65536):
+    """The whole cube of ``w`` generated on a torch device, for workloads
+    too large to draw on the host in reasonable time.  Same distributions as
+    :func:`make_cube` (1..k_max active minerals chosen uniformly, every extra
+    spectrum active when ``extras_active``, Dirichlet(1) weights as normalised
+    exponentials, s_p ~ U[sigma_lo, sigma_hi], Gaussian noise), drawn from a
+    torch generator seeded with ``cube_seed``: a different byte stream.
+    Returns ``(X, sigma)`` as float32 device tensors.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(w.cube_seed)
+    nm, N, P = w.n_minerals, w.N, w.P
+    St = torch.from_numpy(np.ascontiguousarray(S, np.float32)).to(device=device, dtype=torch.float64)
+    X = torch.empty((P, w.L), dtype=torch.float32, device=device)
+    sig = torch.empty(P, dtype=torch.float32, device=device)
+    for p0 in range(0, P, chunk):
+        n = min(chunk, P - p0)
+        k = torch.randint(1, max(w.k_max, 1) + 1, (n, 1), generator=g, device=device)
+        mask = torch.zeros((n, N), dtype=torch.bool, device=device)
+        if nm:
+            ranks = torch.rand((n, nm), generator=g, device=device).argsort(1).argsort(1)
+            mask[:, :nm] = ranks < k
+        if w.extras_active:
+            mask[:, nm:] = True
+        e = torch.empty((n, N), dtype=torch.float64, device=device).exponential_(generator=g)
+        e = torch.where(mask, e, torch.zeros_like(e))
+        A = e / e.sum(1, keepdim=True)
+        sg = torch.rand(n, dtype=torch.float64, generator=g, device=device) * (w.sigma_hi - w.sigma_lo) + w.sigma_lo
+        eps = torch.randn((n, w.L), dtype=torch.float64, generator=g, device=device)
+        X[p0:p0 + n] = (A @ St + sg[:, None] * eps).to(torch.float32)
+        sig[p0:p0 + n] = sg.to(torch.float32)
+    return X, sig
+
+
+BATCH_N = (16, 24, 36, 48, 64, 96)
+BATCH_L = (128, 240, 438)
+
+
+def batch_workloads(n_cubes: int = 200, seed: int = 4242, p_lo: float = 1e3, p_hi: float = 2e5):
+    """The many-cube batch: each cube draws its own library size N from
+    BATCH_N and channel count L from BATCH_L, and a pixel count log-uniform in
+    [p_lo, p_hi]; minerals, extras, abundances and noise as ``precision``
+    (4 extras, 1-4 active minerals, s_p ~ U[0.002, 0.01])."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_cubes):
+        N = int(rng.choice(BATCH_N))
+        L = int(rng.choice(BATCH_L))
+        P = int(round(math.exp(rng.uniform(math.log(p_lo), math.log(p_hi)))))
+        out.append(custom_workload(N, L, P, seed=30_000 + i))
+    return out
 
 
 def custom_workload(N: int, L: int, P: int, seed: int, n_extra: int = 4,

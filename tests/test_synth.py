@@ -1,5 +1,6 @@
 """Generator checks: shapes, value ranges, support sizes, determinism."""
 import numpy as np
+import pytest
 
 from paper_1402_2518_amd import synth
 
@@ -40,3 +41,28 @@ def test_tiny_workload():
     assert X.shape == (1000, 64) and (s == np.float32(0.005)).all()
     k = (A > 0).sum(1)
     assert k.min() == 1 and k.max() == 3
+
+
+def test_device_cube_generator_distribution():
+    torch = pytest.importorskip("torch")
+    w = synth.custom_workload(20, 64, 3000, seed=5)
+    S = synth.make_library(w)
+    X, s = synth.make_cube_device(w, S, "cpu", chunk=1024)
+    X2, s2 = synth.make_cube_device(w, S, "cpu", chunk=1024)
+    assert torch.equal(X, X2) and torch.equal(s, s2)  # seeded
+    assert X.shape == (3000, 64) and X.dtype == torch.float32
+    sn = s.numpy()
+    assert sn.min() >= 0.002 and sn.max() <= 0.01
+    Xh, sh = synth.make_cube(w, S)
+    # same distribution as the host generator: means and spreads agree
+    assert abs(float(X.mean()) - Xh.mean()) < 0.01 and abs(float(X.std()) - Xh.std()) < 0.01
+    assert abs(sn.mean() - sh.mean()) < 3e-4
+
+
+def test_batch_workloads():
+    ws = synth.batch_workloads(200)
+    assert len(ws) == 200
+    assert {w.N for w in ws} == set(synth.BATCH_N) and {w.L for w in ws} == set(synth.BATCH_L)
+    P = np.array([w.P for w in ws])
+    assert P.min() >= 1000 and P.max() <= 200_000 and 5e6 < P.sum() < 1.1e7
+    assert all(w.N <= w.L and w.n_extra == 4 for w in ws)
