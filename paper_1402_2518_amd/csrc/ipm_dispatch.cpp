@@ -55,10 +55,10 @@ static int group_lanes(int nc, bool fp32) {
   return -1;
 }
 
-int ipm_kernel_class(int n, bool fp32) {
+int ipm_kernel_class(int n, bool fp32, bool stable) {
   const int nc = ipm_shape_nc(n);
   if (nc < 0) return -1;
-  if (!fp32 && use_tile(nc)) return 1000 + nc;
+  if (!fp32 && use_tile(nc)) return (stable ? 4000 : 1000) + nc;
   return group_lanes(nc, fp32) > 0 ? (fp32 ? 3000 : 2000) + nc : -1;
 }
 
@@ -95,11 +95,12 @@ int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st) {
   return dispatch(p.n, p, nullptr, mode, fp32, st);
 }
 
-int launch_ipm_batch(int n, int constraint, const IpmBatch& b, int mode, bool fp32, hipStream_t st) {
+int launch_ipm_batch(int n, int constraint, int stable, const IpmBatch& b, int mode, bool fp32, hipStream_t st) {
   if (b.njobs <= 0 || b.blocks <= 0) return 0;
   IpmParams p{};
   p.n = n;
   p.constraint = constraint;
+  p.stable = stable;
   return dispatch(n, p, &b, mode, fp32, st);
 }
 

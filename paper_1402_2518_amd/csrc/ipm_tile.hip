@@ -13,13 +13,18 @@
 // A tile X is kept "stored": lane (x, z) holds X[z][x].  Then one register
 // is A = X and B = X^T at once, and
 //     mfma(stored P, stored Q, stored R) = stored(Q P^T + R),
-// so the trailing update of a block factorisation, H_IJ -= L_IK H_JK^T, is
+// so the trailing update of a block factorisation, H_IJ -= L_IK W_JK^T, is
 // one MFMA on stored tiles with no data movement.  The Newton matrix is
-// factored as a block L D L^T (unit lower L, 4x4 diagonal blocks D_K): the
-// panel is L_IK = H_IK D_K^{-1}, and D_K^{-1} comes from a redundant 4x4
-// L D L^T on every lane of the block after an all-gather by quad broadcasts
-// and row swaps, so there are no square roots and no LDS round trips on the
-// factorisation's critical path.  Vectors that feed the MFMA use the
+// factored as L D L^T with unit lower L and diagonal D, column block by
+// column block: the 4x4 diagonal block is factored redundantly on the 16
+// lanes of its block (after an exchange through LDS) into L_KK diag(d) L_KK^T,
+// the panel is W_JK = H_JK L_KK^{-T} and L_JK = W_JK diag(d)^{-1}, and the
+// trailing update subtracts L_IK W_JK^T.  Keeping L_KK^{-1} and 1/d apart
+// rather than forming the block inverse keeps the factorisation stable when
+// a diagonal block is nearly singular (linearly dependent spectra, such as
+// the +/- pairs of the additional spectra, with small lambda/a): the error
+// of the update then scales with 1/sqrt(d), not 1/d.  No square roots.
+// Vectors that feed the MFMA use the
 // "x layout": lane (x, z) holds element 4I + x of right-hand side z, so up
 // to four right-hand sides ride along (the solve carries u = H^{-1} 1 next to
 // the Newton right-hand side).  Elementwise work uses a compact layout: lane
@@ -89,8 +94,9 @@ struct Tile {
   int x, z, blk;            // lane coordinates
   const double* sG;         // LDS, NP x NP scaled Gram
   double* xch;              // LDS, 16 doubles of this pixel (tile exchange)
-  // Stored tiles of the lower triangle.  After factor(): block L D L^T with
-  // unit lower L; H[id(K, K)] = D_K^{-1}, H[id(I, K)] = -L_IK (I > K).
+  // Stored tiles of the lower triangle.  After factor(): L D L^T with unit
+  // lower L and diagonal D; H[id(K, K)] holds L_KK^{-1} below its diagonal
+  // and 1/d on it (zero above), H[id(I, K)] = -L_IK (I > K).
   double H[NT];
   bool notpd;
 
@@ -147,6 +153,103 @@ struct Tile {
     });
   }
 
+  // The symmetric 4x4 tile M held in stored form (lane (x, z) holds
+  // M[z][x]) as L diag(d) L^T with unit lower L: the block's 16 lanes
+  // exchange the tile through LDS and factor it redundantly.  Each lane
+  // returns entry (z, x) of L^{-1} (1 on the diagonal, 0 above it) in li and
+  // 1 / d_x in rx.
+  __device__ __forceinline__ void ldl4(double h, bool& bad, double& li, double& rx) const {
+    xch[z * 4 + x] = h;
+    lds_sync();
+    const double m00 = xch[0], m10 = xch[4], m11 = xch[5], m20 = xch[8], m21 = xch[9];
+    const double m22 = xch[10], m30 = xch[12], m31 = xch[13], m32 = xch[14], m33 = xch[15];
+    const double d0 = m00;
+    const double r0 = rcpT(d0);
+    const double l10 = m10 * r0, l20 = m20 * r0, l30 = m30 * r0;
+    const double d1 = fmaT(-l10, m10, m11);
+    const double r1 = rcpT(d1);
+    const double t21 = fmaT(-l20, m10, m21), t31 = fmaT(-l30, m10, m31);
+    const double l21 = t21 * r1, l31 = t31 * r1;
+    const double d2 = fmaT(-l21, t21, fmaT(-l20, m20, m22));
+    const double r2 = rcpT(d2);
+    const double t32 = fmaT(-l31, t21, fmaT(-l30, m20, m32));
+    const double l32 = t32 * r2;
+    const double d3 = fmaT(-l32, t32, fmaT(-l31, t31, fmaT(-l30, m30, m33)));
+    const double r3 = rcpT(d3);
+    // pivots positive and finite; for a sum, s - s == 0 is a safe finiteness
+    // test (no product to contract with) and keeps the factor's register
+    // footprint lower than a class test here
+    const double dmin = fmin(fmin(d0, d1), fmin(d2, d3));
+    const double ds = d0 + d1 + d2 + d3;
+    bad |= !(dmin > 0.0) || !(ds == ds && ds - ds == 0.0);
+    // column x of L^{-1}: L v = e_x
+    const double e0 = x == 0 ? 1.0 : 0.0, e1 = x == 1 ? 1.0 : 0.0;
+    const double e2 = x == 2 ? 1.0 : 0.0, e3 = x == 3 ? 1.0 : 0.0;
+    const double v1 = fmaT(-l10, e0, e1);
+    const double v2 = fmaT(-l21, v1, fmaT(-l20, e0, e2));
+    const double v3 = fmaT(-l32, v2, fmaT(-l31, v1, fmaT(-l30, e0, e3)));
+    li = z == 0 ? e0 : (z == 1 ? v1 : (z == 2 ? v2 : v3));
+    rx = x == 0 ? r0 : (x == 1 ? r1 : (x == 2 ? r2 : r3));
+  }
+
+  // tiled right-looking L D L^T of H
+  __device__ __forceinline__ void factor() {
+    bool bad = false;
+    static_for<0, T>([&](auto kk) {
+      constexpr int K = decltype(kk)::value;
+      double li, rx;
+      ldl4(H[id(K, K)], bad, li, rx);
+      const double nrx = -rx;
+      H[id(K, K)] = (x == z) ? rx : li;
+      // Panel W_JK = H_JK L_KK^{-T}, -L_JK = -W_JK diag(d)^{-1}, and trailing
+      // update H_IJ -= L_IK W_JK^T, one column J at a time from the last:
+      // column J needs -L_IK for I >= J (done) and W_JK, so only one W tile
+      // is live.
+      static_for<K + 1, T>([&](auto jj) {
+        constexpr int J = T + K - decltype(jj)::value;
+        const double w = mfma4(li, H[id(J, K)], 0.0);
+        H[id(J, K)] = w * nrx;
+        static_for<J, T>([&](auto ii) {
+          constexpr int I = decltype(ii)::value;
+          H[id(I, J)] = mfma4(w, H[id(I, K)], H[id(I, J)]);
+        });
+      });
+    });
+    notpd = bad;
+  }
+
+  // solve L D L^T X = R in place (x layout, one right-hand side per z)
+  __device__ __forceinline__ void solve(double (&xr)[T]) const {
+    // L y = r: the unit lower diagonal block, then the blocks below it
+    static_for<0, T>([&](auto jj) {
+      constexpr int J = decltype(jj)::value;
+      const double lu = (x == z) ? 1.0 : H[id(J, J)];
+      xr[J] = mfma4(lu, xr[J], 0.0);
+      static_for<J + 1, T>([&](auto ii) {
+        constexpr int I = decltype(ii)::value;
+        xr[I] = mfma4(H[id(I, J)], xr[J], xr[I]);
+      });
+    });
+    // diag(d)^{-1} y
+    static_for<0, T>([&](auto jj) {
+      constexpr int J = decltype(jj)::value;
+      const double dg = (x == z) ? H[id(J, J)] : 0.0;
+      xr[J] = mfma4(dg, xr[J], 0.0);
+    });
+    // L^T x = diag(d)^{-1} y; a transposed tile comes from lane (z, x)
+    const int src = 16 * z + 4 * blk + x;
+    static_for<0, T>([&](auto kk) {
+      constexpr int I = T - 1 - decltype(kk)::value;
+      const double lut = __shfl((x == z) ? 1.0 : H[id(I, I)], src);
+      xr[I] = mfma4(lut, xr[I], 0.0);
+      static_for<0, I>([&](auto jj) {
+        constexpr int J = decltype(jj)::value;
+        const double lt = __shfl(H[id(I, J)], src);
+        xr[J] = mfma4(lt, xr[I], xr[J]);
+      });
+    });
+  }
+
   // -M^{-1}[z][x] for the symmetric 4x4 tile M held in stored form (lane
   // (x, z) holds M[z][x]).  The block's 16 lanes exchange the tile through
   // LDS, factor it redundantly as L diag(d) L^T (unit lower L), and each lane
@@ -188,8 +291,9 @@ struct Tile {
     return z == 0 ? y0 : (z == 1 ? y1 : (z == 2 ? y2 : y3));
   }
 
-  // tiled right-looking block L D L^T of H
-  __device__ __forceinline__ void factor() {
+  // tiled right-looking block L D L^T of H with explicit inverses of the
+  // 4x4 diagonal blocks D_K (panel -L_IK = -H_IK D_K^{-1})
+  __device__ __forceinline__ void factor_inv() {
     bool bad = false;
     static_for<0, T>([&](auto kk) {
       constexpr int K = decltype(kk)::value;
@@ -211,8 +315,8 @@ struct Tile {
     notpd = bad;
   }
 
-  // solve L D L^T X = R in place (x layout, one right-hand side per z)
-  __device__ __forceinline__ void solve(double (&xr)[T]) const {
+  // solve with the factor of factor_inv (identity diagonal blocks of L)
+  __device__ __forceinline__ void solve_inv(double (&xr)[T]) const {
     // L y = r
     static_for<0, T>([&](auto jj) {
       constexpr int J = decltype(jj)::value;
@@ -240,7 +344,9 @@ struct Tile {
 };
 
 // One workgroup's 16 pixels: workgroup wg of the cube described by prm.
-template <int T, int MODE, int CONS>
+// ST: the stable factorisation (factor/solve) rather than explicit inverses
+// of the diagonal blocks (factor_inv/solve_inv).
+template <int T, int MODE, int CONS, bool ST>
 __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) {
   using TL = Tile<T>;
   constexpr int NP = TL::NP;
@@ -342,15 +448,14 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
     // iterations (it would not fit next to the factor).
     asm volatile("" ::: "memory");
     // ---- phase decisions ---------------------------------------------------
-    // g = Gh a is carried from step to step (see the update below); the
-    // finishing step's candidate gets its own product.
-    double gp[C];
-    if (__builtin_amdgcn_ballot_w64(phase == kPol && cand) != 0) {
-      tl.to_x(pa, xl);
-      tl.gmul(xl, gp);
-    }
-    if (phase == kIpm) {
-      double sa = 0.0, sal = 0.0, rdm = 0.0;
+    // g = Gh a is carried from step to step (see the update below).  Where
+    // dependent spectra make the Newton matrix nearly singular, the carried
+    // g drifts from Gh a, so a pixel whose residuals pass the stopping tests
+    // confirms them with an explicit product before it stops; the finishing
+    // step's candidate gets its own product as well.
+    auto residuals = [&](double& rdm) {
+      double sa = 0.0, sal = 0.0;
+      rdm = 0.0;
       static_for<0, C>([&](auto mm) {
         constexpr int m = decltype(mm)::value;
         rd[m] = vm[m] ? (g[m] - bh[m] - lam[m] + nu) : 0.0;
@@ -361,11 +466,33 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
       rp = pos ? 0.0 : bsum(sa) + s - 1.0;
       mu = (bsum(sal) + s * nu) * inv_np;
       rdm = bmax(rdm);
-      bool conv;
+    };
+    auto stops = [&](double rdm) {
       if constexpr (MODE == kStage1)
-        conv = mu <= fmax(tol_mu, prm.mu_switch);
+        return mu <= fmax(tol_mu, prm.mu_switch);
       else
-        conv = mu <= tol_mu && rdm <= tol_d * (1.0 + bhmax) && fabs(rp) <= tol_p;
+        return mu <= tol_mu && rdm <= tol_d * (1.0 + bhmax) && fabs(rp) <= tol_p;
+    };
+    double rdm = 0.0;
+    bool conv = false;
+    if (phase == kIpm) {
+      residuals(rdm);
+      conv = stops(rdm);
+    }
+    const bool confirm = MODE != kStage1 && phase == kIpm && conv;
+    double gp[C];
+    if (__builtin_amdgcn_ballot_w64(confirm || (phase == kPol && cand)) != 0) {
+      double v[C];
+      static_for<0, C>([&](auto mm) { v[mm] = confirm ? a[mm] : pa[mm]; });
+      tl.to_x(v, xl);
+      tl.gmul(xl, gp);
+    }
+    if (confirm) {
+      static_for<0, C>([&](auto mm) { g[mm] = gp[mm]; });
+      residuals(rdm);
+      conv = stops(rdm);
+    }
+    if (phase == kIpm) {
       if (conv) {
         converged = true;
         phase = kPol;
@@ -444,7 +571,7 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
     });
     tl.to_x(D, xl);
     tl.form(xl);
-    tl.factor();
+    if constexpr (ST) tl.factor(); else tl.factor_inv();
     if (phase != kDone && tl.notpd) {
       if (phase == kIpm) flags |= kPxNotPd;
       phase = kDone;
@@ -463,7 +590,7 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
         xl[I] = (z == 1) ? one : xl[I];
       });
     }
-    tl.solve(xl);
+    if constexpr (ST) tl.solve(xl); else tl.solve_inv(xl);
     tl.template from_x<0>(xl, dx);
     tl.template from_x<1>(xl, u);
     double su = 0.0, sw = 0.0;
@@ -528,7 +655,7 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
       dx[m] = vm[m] ? -rd[m] - dla[m] : 0.0;
     });
     tl.to_x(dx, xl);
-    tl.solve(xl);
+    if constexpr (ST) tl.solve(xl); else tl.solve_inv(xl);
     tl.template from_x<0>(xl, dx);
     double sw2 = 0.0;
     static_for<0, C>([&](auto mm) { sw2 += dx[mm]; });
@@ -632,50 +759,66 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
   }
 }
 
-template <int T, int MODE, int CONS>
-__global__ __launch_bounds__(256, 2) void ipm_tile_kernel(IpmParams prm) {
-  ipm_tile_body<T, MODE, CONS>(prm, blockIdx.x);
+// waves per SIMD the register budget is sized for: two up to T = 9; beyond,
+// the tiles alone need more than half of the 512 registers of a lane
+template <int T>
+constexpr int kTileWaves = T <= 9 ? 2 : 1;
+
+template <int T, int MODE, int CONS, bool ST>
+__global__ __launch_bounds__(256, kTileWaves<T>) void ipm_tile_kernel(IpmParams prm) {
+  ipm_tile_body<T, MODE, CONS, ST>(prm, blockIdx.x);
 }
 
 // Several cubes in one launch (one job per cube, blocks assigned by start).
-template <int T, int MODE, int CONS>
-__global__ __launch_bounds__(256, 2) void ipm_tile_batch_kernel(const IpmParams* __restrict__ jobs,
-                                                                 const int64_t* __restrict__ start, int njobs) {
+template <int T, int MODE, int CONS, bool ST>
+__global__ __launch_bounds__(256, kTileWaves<T>) void ipm_tile_batch_kernel(const IpmParams* __restrict__ jobs,
+                                                                             const int64_t* __restrict__ start,
+                                                                             int njobs) {
   const int j = job_of(start, njobs, blockIdx.x);
   const IpmParams prm = uniform_copy(jobs + j);
-  ipm_tile_body<T, MODE, CONS>(prm, (int64_t)blockIdx.x - start[j]);
+  ipm_tile_body<T, MODE, CONS, ST>(prm, (int64_t)blockIdx.x - start[j]);
 }
 
-template <int T, int MODE, int CONS>
+template <int T, int MODE, int CONS, bool ST>
 static void launch_tile_m(const IpmParams& p, const IpmBatch* b, hipStream_t st) {
   if (b)
-    hipLaunchKernelGGL((ipm_tile_batch_kernel<T, MODE, CONS>), dim3((unsigned)b->blocks), dim3(256), 0, st, b->jobs,
-                       b->start, b->njobs);
+    hipLaunchKernelGGL((ipm_tile_batch_kernel<T, MODE, CONS, ST>), dim3((unsigned)b->blocks), dim3(256), 0, st,
+                       b->jobs, b->start, b->njobs);
   else
-    hipLaunchKernelGGL((ipm_tile_kernel<T, MODE, CONS>), dim3((unsigned)((p.P + 15) / 16)), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((ipm_tile_kernel<T, MODE, CONS, ST>), dim3((unsigned)((p.P + 15) / 16)), dim3(256), 0, st, p);
 }
 
-template <int T, int CONS>
+template <int T, int CONS, bool ST>
 static int launch_tile_c(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
   if (mode == kFull)
-    launch_tile_m<T, kFull, CONS>(p, b, st);
+    launch_tile_m<T, kFull, CONS, ST>(p, b, st);
   else if (mode == kStage2)
-    launch_tile_m<T, kStage2, CONS>(p, b, st);
+    launch_tile_m<T, kStage2, CONS, ST>(p, b, st);
   else
     return -5;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-// b == nullptr: one cube described by p; else the jobs of b (p only gives
-// the constraint option, shared by every job).
-template <int T>
-static int launch_tile(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
+template <int T, bool ST>
+static int launch_tile_s(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
   switch (p.constraint) {
-    case kSto: return launch_tile_c<T, kSto>(p, b, mode, st);
-    case kSlo: return launch_tile_c<T, kSlo>(p, b, mode, st);
-    case kPos: return launch_tile_c<T, kPos>(p, b, mode, st);
+    case kSto: return launch_tile_c<T, kSto, ST>(p, b, mode, st);
+    case kSlo: return launch_tile_c<T, kSlo, ST>(p, b, mode, st);
+    case kPos: return launch_tile_c<T, kPos, ST>(p, b, mode, st);
   }
   return -1;
+}
+
+// b == nullptr: one cube described by p; else the jobs of b (p only gives
+// the constraint option and the factorisation, shared by every job).  The
+// explicit-inverse factorisation is built up to T = 9 only, for libraries
+// whose scaled Gram matrix is well conditioned.
+template <int T>
+static int launch_tile(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st) {
+  if constexpr (T <= 9) {
+    if (!p.stable) return launch_tile_s<T, false>(p, b, mode, st);
+  }
+  return launch_tile_s<T, true>(p, b, mode, st);
 }
 
 #if defined(LM_TILE_T)

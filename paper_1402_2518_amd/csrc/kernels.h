@@ -41,6 +41,7 @@ struct IpmParams {
   int maxit;
   int max_polish;
   int constraint;       // kSto, kSlo or kPos
+  int stable;           // tile kernels: 1 = factorisation safe for nearly singular diagonal blocks
   double tol_mu, tol_d, tol_p, eta, lambda0, tau, deg_tol, mu_switch;
   // hand-over state between the FP32 and FP64 stages
   double* st_a;         // P x n
@@ -70,11 +71,11 @@ struct IpmBatch {
 // ipm_dispatch.cpp: picks the compiled shape for n and precision.
 int ipm_shape_nc(int n);                      // padded size NC used for a library of size n
 int ipm_pixels_per_block(int n, bool fp32);   // pixels of one workgroup for that shape
-int ipm_kernel_class(int n, bool fp32);       // launches of equal class can share a batch
+int ipm_kernel_class(int n, bool fp32, bool stable);  // launches of equal class can share a batch
 int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st);
-// batched: every job of b has a library with ipm_kernel_class(n, fp32) equal
-// to that of n; constraint as in IpmParams
-int launch_ipm_batch(int n, int constraint, const IpmBatch& b, int mode, bool fp32, hipStream_t st);
+// batched: every job of b has a library with ipm_kernel_class(n, fp32,
+// stable) equal to that of n; constraint and stable as in IpmParams
+int launch_ipm_batch(int n, int constraint, int stable, const IpmBatch& b, int mode, bool fp32, hipStream_t st);
 
 // gemm.hip
 // One cube of a batched projection launch: bh = Y W (and c = y^T y, or

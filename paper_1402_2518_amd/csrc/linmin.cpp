@@ -21,6 +21,7 @@
 
 struct linmin_lib_s {
   int L, N, NC, ldw, dev;
+  int stable;    // Gh has an eigenvalue below kNearlySingular: tile kernels use the stable factorisation
   double gamma;
   double* Wh;    // L x ldw, W / gamma
   double* Gh64;  // NC x NC, G / gamma padded with identity
@@ -60,6 +61,33 @@ void free_lib(linmin_lib l) {
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Below this smallest eigenvalue of the scaled Gram matrix Gh = G / gamma
+// (largest diagonal 1), a diagonal block of the Newton matrix Gh + diag(D)
+// can be so nearly singular that an explicit 4x4 block inverse loses the
+// next pivots: its error is about eps / lambda_min, which must stay well
+// below lambda_min, i.e. lambda_min >> sqrt(eps) = 1.5e-8.
+constexpr double kNearlySingular = 1e-7;
+
+// Kernel choice at library set-up: whether Gh - tau I is not positive
+// definite (a Cholesky factorisation of it breaks down), i.e. Gh has an
+// eigenvalue below tau.  G is N x N row-major and symmetric.
+bool nearly_singular(const double* G, int N, double gamma, double tau) {
+  std::vector<double> Lc((size_t)N * N, 0.0);
+  for (int j = 0; j < N; ++j) {
+    double d = G[(size_t)j * N + j] / gamma - tau;
+    for (int k = 0; k < j; ++k) d -= Lc[(size_t)j * N + k] * Lc[(size_t)j * N + k];
+    if (!(d > 0.0) || !isfinite(d)) return true;
+    d = sqrt(d);
+    Lc[(size_t)j * N + j] = d;
+    for (int i = j + 1; i < N; ++i) {
+      double v = G[(size_t)i * N + j] / gamma;
+      for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * N + k] * Lc[(size_t)j * N + k];
+      Lc[(size_t)i * N + j] = v / d;
+    }
+  }
+  return false;
+}
 
 struct Work {
   size_t bh, c, dcov, dcorner, big, st_a, st_lam, st_nu, st_s, st_it, st_flag, status, total;
@@ -110,6 +138,7 @@ lm::IpmParams make_ipm(const linmin_lib_s* lib, int64_t P, const float* sigma, d
   prm.maxit = o.maxit;
   prm.max_polish = o.max_polish;
   prm.constraint = o.constraint;
+  prm.stable = lib->stable;
   prm.tol_mu = o.tol_mu;
   prm.tol_d = o.tol_d;
   prm.tol_p = o.tol_p;
@@ -269,6 +298,9 @@ int linmin_create_library(const float* S, int L, int N, const double* noise_cov,
       rc = LINMIN_ENOTSPD;
       goto fail;
     }
+    std::vector<double> Gh((size_t)N * N);
+    TRY(hip_ok(hipMemcpy(Gh.data(), lib->G, sizeof(double) * Gh.size(), hipMemcpyDeviceToHost)));
+    lib->stable = nearly_singular(Gh.data(), N, lib->gamma, kNearlySingular) ? 1 : 0;
   }
   (void)hipFree(dS);
   (void)hipFree(dC);
@@ -403,7 +435,7 @@ struct linmin_batch_s {
   std::vector<Proj> proj;
   Proj quad{0, nullptr, nullptr, 0, 0};
   struct Ipm {
-    int n, mode;
+    int n, mode, stable;
     bool fp32;
     lm::IpmBatch b;
   };
@@ -462,7 +494,7 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
     const linmin_job& J = jobs[j];
     if (!J.lib || J.P < 0 || J.lib->dev != dev) return LINMIN_EINVAL;
     if (J.P > 0 && (!J.cube || !J.out_coeffs)) return LINMIN_EINVAL;
-    if (lm::ipm_kernel_class(J.lib->N, false) < 0 || lm::ipm_kernel_class(J.lib->N, true) < 0)
+    if (lm::ipm_kernel_class(J.lib->N, false, false) < 0 || lm::ipm_kernel_class(J.lib->N, true, false) < 0)
       return LINMIN_EUNSUPPORTED;
   }
   const bool mixed = o.precision == LINMIN_MIXED;
@@ -514,12 +546,12 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
     if (lib->Ci) quad.add(pj, cdiv(P, lm::proj_pixels_per_block()));
 
     lm::IpmParams prm = make_ipm(lib, P, J.sigma, J.out_coeffs, status, J.iters, J.objective, o, w, ws, want_cov);
-    const int k2 = lm::ipm_kernel_class(lib->N, false);
+    const int k2 = lm::ipm_kernel_class(lib->N, false, lib->stable != 0);
     prm.Gh = lib->Gh64;
     ipm2[k2].add(prm, cdiv(P, lm::ipm_pixels_per_block(lib->N, false)));
     class_n2[k2] = lib->N;
     if (mixed) {
-      const int k1 = lm::ipm_kernel_class(lib->N, true);
+      const int k1 = lm::ipm_kernel_class(lib->N, true, lib->stable != 0);
       prm.Gh = lib->Gh32;
       ipm1[k1].add(prm, cdiv(P, lm::ipm_pixels_per_block(lib->N, true)));
       class_n1[k1] = lib->N;
@@ -564,7 +596,7 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   auto add_ipm = [&](std::map<int, Group<lm::IpmParams>>& m, std::map<int, int>& nmap, int mode, bool fp32) {
     for (auto& kv : m) {
       const auto& g = kv.second;
-      linmin_batch_s::Ipm e{nmap[kv.first], mode, fp32,
+      linmin_batch_s::Ipm e{nmap[kv.first], mode, g.jobs.front().stable, fp32,
                             {(const lm::IpmParams*)(t + g.jobs_at), (const int64_t*)(t + g.start_at),
                              (int)g.jobs.size(), g.units()}};
       b->ipm.push_back(e);
@@ -607,7 +639,7 @@ int linmin_batch_run(linmin_batch b, void* stream) {
   if (rc == LINMIN_OK) rc = mark(1);
   for (size_t i = 0; rc == LINMIN_OK && i < b->ipm.size(); ++i) {
     const auto& g = b->ipm[i];
-    rc = from_launch(lm::launch_ipm_batch(g.n, b->o.constraint, g.b, g.mode, g.fp32, st));
+    rc = from_launch(lm::launch_ipm_batch(g.n, b->o.constraint, g.stable, g.b, g.mode, g.fp32, st));
   }
   if (rc == LINMIN_OK) rc = mark(2);
   if (rc == LINMIN_OK) rc = from_launch(lm::launch_cov_batch(b->cov[0], b->cov[1], b->cov[2], st));
