@@ -11,6 +11,7 @@ full FP64 covariance.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -130,6 +131,68 @@ def batch_leg(args, dev, stream):
     return out
 
 
+def serve_leg(args, dev):
+    """Poisson arrivals of cubes of 8 resident libraries through the request
+    loop: latency under load, and sampled requests checked against the same
+    request served alone and against the oracle."""
+    import torch
+    import oracle
+    from paper_1402_2518_amd import linmin, serve, synth
+
+    rng = np.random.default_rng(5150)
+    P_POOL = 200_000
+    libs, pools, host = {}, {}, {}
+    for k in range(8):
+        N, L = int(rng.choice(synth.BATCH_N)), int(rng.choice(synth.BATCH_L))
+        w = synth.custom_workload(N, L, P_POOL, seed=40_000 + k)
+        S = synth.make_library(w)
+        libs[k] = linmin.Library(S)
+        pools[k] = synth.make_cube_device(w, S, dev)
+        host[k] = S
+        libs[k].unmix(pools[k][0][:64], pools[k][1][:64], cov="full")  # loads the kernels
+    torch.cuda.synchronize()
+    t = serve.poisson_arrivals(args.serve_rate, args.serve_seconds, rng)
+    sample = set(rng.choice(len(t), size=min(12, len(t)), replace=False).tolist())
+    reqs = []
+    for rid, ta in enumerate(t):
+        k = int(rng.integers(0, 8))
+        P = int(round(math.exp(rng.uniform(math.log(1e3), math.log(2e5)))))
+        off = int(rng.integers(0, P_POOL - P + 1))
+        X, s = pools[k]
+        r = serve.Request(rid, k, X[off:off + P], s[off:off + P], float(ta), keep=rid in sample)
+        reqs.append(r)
+    srv = serve.Server(libs, streams=4, slots=8, hbm_budget=96 << 30, precision="fp64", cov="full")
+    print(f"# serving: {len(reqs)} requests over {args.serve_seconds:.0f}s", file=sys.stderr, flush=True)
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    out = serve.latency_summary(done)
+    out.update({"offered_rate_per_s": args.serve_rate, "seconds": args.serve_seconds, "libraries": 8,
+                "libraries_NL": [[libs[k].N, libs[k].L] for k in range(8)], "cov_layout": "full",
+                "precision": "fp64", "slots": srv.slots, "streams": len(srv.streams),
+                "hbm_budget_bytes": srv.budget, "max_running": srv.stats["max_running"],
+                "max_bytes_in_use": srv.stats["max_bytes"],
+                "inputs": "device-resident cube pools (200,000 pixels per library), requests are row ranges"})
+    same, err = True, 0.0
+    for r in done:
+        if not r.keep:
+            continue
+        alone = libs[r.lib].unmix(r.cube, r.sigma, precision="fp64", cov="full")
+        torch.cuda.synchronize()
+        same &= all(torch.equal(r.out[k].nan_to_num(3.5), alone[k].nan_to_num(3.5)) for k in ("a", "cov", "status"))
+        X8 = r.cube[:4].cpu().numpy()
+        s8 = r.sigma[:4].cpu().numpy()
+        ro = oracle.unmix(host[r.lib], X8, s8, cov=False)
+        err = max(err, float(np.abs(r.out["a"][:4].cpu().numpy() - ro["a"]).max()))
+        r.out = None
+    out["sampled_requests"] = len(sample)
+    out["identical_alone_and_in_mix"] = bool(same)
+    out["max_abs_coeff_err_vs_oracle_sample"] = err
+    print(f"# serving: {out}", file=sys.stderr, flush=True)
+    for lib in libs.values():
+        lib.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +207,9 @@ def main():
     ap.add_argument("--batch-cubes", type=int, default=200,
                     help="cubes in the many-cube batch leg (0 = skip)")
     ap.add_argument("--batch-runs", type=int, default=2, help="timed runs of the batch leg")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson arrival stream of the serving leg (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="cubes per second arriving")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -282,6 +348,10 @@ def main():
         del out_cov
         torch.cuda.empty_cache()
         result["batch"] = batch_leg(args, dev, stream)
+
+    if args.serve_seconds > 0:
+        torch.cuda.empty_cache()
+        result["serving"] = serve_leg(args, dev)
 
     if not args.no_cpu:
         oracle.build(force=False)

@@ -1,0 +1,157 @@
+"""Request loop for unmixing cubes as they arrive (continuous batching).
+
+Libraries stay resident on the device with their Gram matrices (one
+:class:`linmin.Library` each).  A request names a library and a device cube.
+Requests wait in arrival order; the head of the queue is admitted as soon as
+an execution slot is free and its HBM footprint (outputs and the call's
+workspace) fits in the budget next to the requests already running.  An
+admitted request is one ``linmin_unmix`` call on one of a few HIP streams, so
+requests of different libraries and sizes run on the device at the same time
+and new ones start while earlier ones are still running.  Every pixel is
+solved independently, so a request's result does not depend on what else was
+running.
+
+Host-side scheduling only: the arithmetic is in the library's kernels.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from collections import deque
+
+import numpy as np
+
+from . import linmin
+
+_COV_PER = {None: lambda n: 0, "none": lambda n: 0, "full": lambda n: n * n,
+            "packed": lambda n: n * (n + 1) // 2, "diag": lambda n: n}
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    lib: str             # key of a resident library
+    cube: object         # P x L float32 device tensor
+    sigma: object        # P float32 device tensor or None
+    arrival: float       # seconds from the start of the run
+    keep: bool = True    # keep the outputs after completion
+    # filled by the server
+    t_start: float = float("nan")
+    t_done: float = float("nan")
+    footprint: int = 0
+    out: dict | None = None
+
+
+def footprint(lib: linmin.Library, P: int, precision: str, cov: str | None) -> int:
+    """Device bytes a request holds while it runs: its outputs and the
+    workspace of the call."""
+    n = lib.N
+    outs = P * (8 * n + 8 * _COV_PER[cov](n) + 1 + 4 + 8)
+    return outs + lib.workspace_bytes(P, precision, cov)
+
+
+def admissible(head_bytes: int, used_bytes: int, budget: int, running: int, slots: int) -> bool:
+    """Admission rule: a free slot and room in the HBM budget (a request
+    larger than the whole budget is admitted alone, so it cannot wait
+    forever)."""
+    if running >= slots:
+        return False
+    if running == 0:
+        return True
+    return used_bytes + head_bytes <= budget
+
+
+class Server:
+    def __init__(self, libraries: dict, streams: int = 4, slots: int = 8, hbm_budget: int = 64 << 30,
+                 precision: str = "fp64", cov: str | None = "full"):
+        import torch
+        self.libs = libraries
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.slots = slots
+        self.budget = int(hbm_budget)
+        self.precision = precision
+        self.cov = cov
+        self.stats = {"max_running": 0, "max_bytes": 0}
+
+    def _launch(self, r: Request, k: int):
+        import torch
+        lib = self.libs[r.lib]
+        P, n = r.cube.shape[0], lib.N
+        st = self.streams[k % len(self.streams)]
+        with torch.cuda.stream(st):
+            dev = r.cube.device
+            shp = {None: None, "none": None, "full": (P, n, n), "packed": (P, n * (n + 1) // 2),
+                   "diag": (P, n)}[self.cov]
+            out = {"a": torch.empty((P, n), dtype=torch.float64, device=dev),
+                   "cov": None if shp is None else torch.empty(shp, dtype=torch.float64, device=dev),
+                   "status": torch.empty(P, dtype=torch.uint8, device=dev),
+                   "iters": torch.empty(P, dtype=torch.int32, device=dev),
+                   "objective": torch.empty(P, dtype=torch.float64, device=dev)}
+            lib.unmix_into(r.cube, r.sigma, out["a"], out["cov"], out["status"], out["iters"], out["objective"],
+                           precision=self.precision, cov=self.cov, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return out, ev
+
+    def run(self, requests: list[Request], poll_s: float = 2e-4) -> list[Request]:
+        """Serve ``requests`` (their arrival times relative to now); return
+        them completed, in completion order."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: deque[Request] = deque()
+        running: list[tuple[Request, object]] = []
+        done: list[Request] = []
+        used = 0
+        k = 0
+        for r in pending:
+            r.footprint = footprint(self.libs[r.lib], r.cube.shape[0], self.precision, self.cov)
+        t0 = time.perf_counter()
+        while pending or waiting or running:
+            now = time.perf_counter() - t0
+            busy = False
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            for item in list(running):
+                r, ev = item
+                if ev.query():
+                    r.t_done = time.perf_counter() - t0
+                    used -= r.footprint
+                    running.remove(item)
+                    if not r.keep:
+                        r.out = None
+                    done.append(r)
+                    busy = True
+            while waiting and admissible(waiting[0].footprint, used, self.budget, len(running), self.slots):
+                r = waiting.popleft()
+                r.t_start = time.perf_counter() - t0
+                r.out, ev = self._launch(r, k)
+                k += 1
+                used += r.footprint
+                running.append((r, ev))
+                self.stats["max_running"] = max(self.stats["max_running"], len(running))
+                self.stats["max_bytes"] = max(self.stats["max_bytes"], used)
+                busy = True
+            if not busy:
+                time.sleep(poll_s)
+        return done
+
+
+def poisson_arrivals(rate: float, seconds: float, rng: np.random.Generator) -> np.ndarray:
+    """Arrival times of a Poisson process of the given rate on [0, seconds)."""
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            return np.array(out)
+        out.append(t)
+
+
+def latency_summary(done: list[Request]) -> dict:
+    lat = np.array([r.t_done - r.arrival for r in done]) * 1e3
+    wait = np.array([r.t_start - r.arrival for r in done]) * 1e3
+    pix = sum(int(r.cube.shape[0]) for r in done)
+    span = max(r.t_done for r in done) - min(r.arrival for r in done)
+    return {"requests": len(done), "pixels": pix, "pixels_per_s": pix / span,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "queue_wait_ms": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+            "span_s": span}

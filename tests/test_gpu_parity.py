@@ -465,3 +465,52 @@ def test_dependent_spectra_first(dev, constraint):
     exact = (g["status"] == 0) & (r["status"] == 0)
     if exact.any():
         assert np.abs(g["a"][exact] - r["a"][exact]).max() <= 1e-6
+
+
+def test_serving_mix_identical_alone(dev):
+    """Requests of four resident libraries (N = 8..96) arriving within 50 ms
+    run concurrently under an HBM budget that admits only some at a time;
+    each result equals the same request served alone, bit for bit, and
+    sampled pixels match the oracle."""
+    from paper_1402_2518_amd import linmin, serve
+    _say("[gpu] serving loop: 24 overlapping requests")
+    rng = np.random.default_rng(77)
+    shapes = [(8, 64), (36, 240), (48, 128), (96, 128)]
+    libs, pools, hostS = {}, {}, {}
+    for i, (N, L) in enumerate(shapes):
+        w = synth.custom_workload(N, L, 4000, seed=900 + i)
+        S = synth.make_library(w)
+        X, s = synth.make_cube(w)
+        libs[i] = linmin.Library(S)
+        pools[i] = (torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev), X, s)
+        hostS[i] = S
+    reqs = []
+    for rid in range(24):
+        k = int(rng.integers(0, len(shapes)))
+        P = int(round(np.exp(rng.uniform(np.log(50), np.log(3000)))))
+        off = int(rng.integers(0, 4000 - P + 1))
+        Xd, sd, _, _ = pools[k]
+        reqs.append(serve.Request(rid, k, Xd[off:off + P], sd[off:off + P], arrival=float(rng.uniform(0, 0.05))))
+        reqs[-1].off = off
+    fps = sorted(serve.footprint(libs[r.lib], r.cube.shape[0], "fp64", "full") for r in reqs)
+    budget = 3 * fps[len(fps) // 2]
+    srv = serve.Server(libs, streams=4, slots=6, hbm_budget=budget, cov="full")
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in done) == list(range(24))
+    assert srv.stats["max_running"] >= 2
+    assert srv.stats["max_bytes"] <= max(budget, fps[-1])
+    for r in done:
+        alone = libs[r.lib].unmix(r.cube, r.sigma, precision="fp64", cov="full")
+        torch.cuda.synchronize()
+        for key in ("a", "cov", "status", "iters", "objective"):
+            assert torch.equal(r.out[key].nan_to_num(3.5), alone[key].nan_to_num(3.5)), (r.rid, key)
+    for r in done[:6]:
+        _, _, X, s = pools[r.lib]
+        k = min(8, r.cube.shape[0])
+        ro = oracle.unmix(hostS[r.lib], X[r.off:r.off + k], s[r.off:r.off + k], cov=False)
+        assert np.abs(r.out["a"][:k].cpu().numpy() - ro["a"]).max() <= 1e-6
+    summary = serve.latency_summary(done)
+    _say(f"  {summary}")
+    for lib in libs.values():
+        lib.close()
