@@ -168,3 +168,72 @@ def extra_spectra(L: int, n: int = 4, wavelengths: np.ndarray | None = None) -> 
             c, s = np.cos(2 * np.pi * cycles * t), np.sin(2 * np.pi * cycles * t)
             rows += [c, s, -c, -s]
     return np.stack(rows)
+
+
+# ---------------------------------------------------------------------------
+# Detection post-processing (Sec. 3.1 eq. 8 and the rules of Sec. 4)
+# ---------------------------------------------------------------------------
+def rms_map(S: np.ndarray, X: np.ndarray, A: np.ndarray, C: np.ndarray | None = None) -> np.ndarray:
+    """Root-mean-square of each pixel's fit residual over its L channels, in
+    the renormalised space of Sec. 2.3: with C^{-1} = Lc Lc^T the residual is
+    (x - a S) Lc; for C = I the plain reflectance residual."""
+    Sd, Xd = np.asarray(S, np.float64), np.asarray(X, np.float64)
+    R = Xd - np.asarray(A, np.float64) @ Sd
+    if C is not None:
+        Lc = np.linalg.cholesky(np.linalg.inv(np.asarray(C, np.float64)))
+        R = R @ Lc
+    return np.sqrt((R * R).sum(1) / Sd.shape[1])
+
+
+def sigma1_map(cov: np.ndarray) -> np.ndarray:
+    """1-sigma error of every coefficient: square roots of the covariance
+    diagonal (P x N from P x N x N)."""
+    return np.sqrt(np.maximum(np.diagonal(np.asarray(cov, np.float64), axis1=1, axis2=2), 0.0))
+
+
+def thresholds(A: np.ndarray, present: np.ndarray) -> np.ndarray:
+    """Detection threshold of eq. 8 for every endmember i: half the sum of
+    (mean - 2 std) of its coefficients on the pixels where it is present and
+    (mean + 6 std) where it is absent; population standard deviations.  NaN
+    for an endmember without present or without absent pixels."""
+    A = np.asarray(A, np.float64)
+    present = np.asarray(present, bool)
+    out = np.full(A.shape[1], np.nan)
+    for i in range(A.shape[1]):
+        pos, neg = A[present[:, i], i], A[~present[:, i], i]
+        if len(pos) and len(neg):
+            out[i] = 0.5 * (pos.mean() - 2.0 * pos.std() + neg.mean() + 6.0 * neg.std())
+    return out
+
+
+def detect(A: np.ndarray, sigma1: np.ndarray, rms: np.ndarray, thr: np.ndarray, rms_max: float) -> np.ndarray:
+    """Detection rules of Sec. 4: endmember i is detected in pixel p when its
+    coefficient exceeds the threshold, its 1-sigma error is below the
+    coefficient, and the pixel's RMS is below the noise level rms_max."""
+    A = np.asarray(A, np.float64)
+    return (A > np.asarray(thr)[None, :]) & (np.asarray(sigma1) < A) & (np.asarray(rms)[:, None] < rms_max)
+
+
+def second_pass(S: np.ndarray, X: np.ndarray, sigma, keep: np.ndarray, C=None, constraint: int = STO):
+    """Second pass of the conclusion: each pixel unmixed again with only the
+    spectra kept for it (keep: P x N bool), by the oracle on that sub-library;
+    coefficients and covariance scattered back to N (zeros elsewhere).
+    Pixels that keep no spectrum get NaN."""
+    X = np.asarray(X)
+    P, N = X.shape[0], S.shape[0]
+    a = np.zeros((P, N))
+    cov = np.zeros((P, N, N))
+    status = np.zeros(P, np.uint8)
+    F = np.zeros(P)
+    for p in range(P):
+        idx = np.flatnonzero(keep[p])
+        if len(idx) == 0:
+            a[p], cov[p], F[p] = np.nan, np.nan, np.nan
+            continue
+        s = None if sigma is None else np.asarray(sigma)[p:p + 1]
+        r = unmix(np.ascontiguousarray(S[idx]), X[p:p + 1], s, C=C, constraint=constraint)
+        a[p, idx] = r["a"][0]
+        cov[p][np.ix_(idx, idx)] = r["cov"][0]
+        status[p] = r["status"][0]
+        F[p] = r["F"][0]
+    return {"a": a, "cov": cov, "status": status, "F": F}
