@@ -105,6 +105,14 @@ typedef struct {
                             stream before the projections, before the
                             interior-point solve, before the covariance pass
                             and after it (stage timing without a profiler) */
+    const uint8_t *keep; /* device, P x N or NULL: the second pass of the
+                            conclusion (unmix again with the detected spectra
+                            only).  Nonzero keeps spectrum i for pixel p; the
+                            others are held at a_i = 0 (their projection is
+                            replaced by one large negative enough that the
+                            result is the minimiser over the kept spectra).
+                            A pixel that keeps none is reported
+                            LINMIN_PX_NONFINITE.  Batches reject it. */
 } linmin_opts;
 
 /* Fill *opts with the defaults quoted above (pointer members NULL). */
@@ -216,7 +224,8 @@ typedef struct linmin_batch_s *linmin_batch;
  *                 point to are not, and must stay valid for every run).
  *   opts          NULL for defaults; its precision, layout, constraint and
  *                 tolerances apply to every job; its status / iters /
- *                 objective members are ignored (each job carries its own);
+ *                 objective members are ignored (each job carries its own)
+ *                 and its keep member must be NULL;
  *                 stage_events, if set, are recorded by every run.
  * The libraries must outlive the batch.  Errors: EINVAL (NULL out, a job
  * with a NULL library or a library of another device, P < 0, NULL cube or
@@ -239,6 +248,41 @@ size_t linmin_batch_device_bytes(linmin_batch batch);
 
 /* Release a batch (after all its runs have completed). */
 int linmin_batch_destroy(linmin_batch batch);
+
+/*
+ * Detection post-processing (Sec. 3.1 and 4).  All pointers are device
+ * memory; every call is asynchronous on stream (NULL: default stream).
+ *
+ * linmin_error_maps: per pixel the RMS of the fit, rms_p = s_p sqrt(F_p / L)
+ * (the root mean square over the L channels of the residual in the
+ * renormalised space of Sec. 2.3, from the objective F of linmin_unmix and
+ * sigma as given to it), and per coefficient the 1-sigma error, the square
+ * root of the covariance diagonal (cov in cov_layout as written by
+ * linmin_unmix).  rms (P) or sigma1 (P x N) may be NULL to skip it; NaN
+ * inputs give NaN.  Errors: EINVAL.
+ */
+int linmin_error_maps(linmin_lib lib, int64_t P, const double *objective, const float *sigma, const double *cov,
+                      int cov_layout, double *rms, double *sigma1, void *stream);
+
+/*
+ * Detection threshold of eq. 8 for each of N endmembers, from coefficients
+ * (P x N) of pixels where each endmember is known present (present: P x N,
+ * nonzero) or absent: half the sum of (mean - 2 std) over present pixels and
+ * (mean + 6 std) over absent ones, population standard deviations; NaN for
+ * an endmember with no present or no absent pixel.  thresholds: N doubles.
+ * Takes a small stream-ordered workspace.  Errors: EINVAL, ENOMEM, EHIP.
+ */
+int linmin_thresholds(int N, int64_t P, const double *coeffs, const uint8_t *present, double *thresholds,
+                      void *stream);
+
+/*
+ * Detection rules of Sec. 4: detected[p][i] = 1 when coeffs[p][i] exceeds
+ * thresholds[i], sigma1[p][i] < coeffs[p][i] (a significant coefficient) and
+ * rms[p] < rms_max (a fit at the noise level), else 0.  P x N bytes.  The
+ * result may serve as linmin_opts.keep of a second pass.  Errors: EINVAL.
+ */
+int linmin_detect(int N, int64_t P, const double *coeffs, const double *sigma1, const double *rms,
+                  const double *thresholds, double rms_max, uint8_t *detected, void *stream);
 
 /* Release a library (after all work using it has completed). */
 int linmin_destroy_library(linmin_lib lib);

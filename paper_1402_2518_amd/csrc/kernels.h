@@ -138,6 +138,16 @@ int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, 
                const float* sigma, double gamma, const uint8_t* status_or_null, int layout,
                double* out_cov, uint8_t* big, hipStream_t st);
 
+// detect.hip
+int launch_error_maps(int n, int64_t P, int L, const double* objective, const float* sigma, const double* cov,
+                      int layout, double* rms, double* sigma1, hipStream_t st);
+size_t thresholds_workspace_bytes(int n, int64_t P);
+int launch_thresholds(int n, int64_t P, const double* A, const uint8_t* present, double* thr, double* ws,
+                      hipStream_t st);
+int launch_detect(int n, int64_t P, const double* A, const double* sigma1, const double* rms, const double* thr,
+                  double rms_max, uint8_t* det, hipStream_t st);
+int launch_keep(int n, int64_t P, const uint8_t* keep, const double* c, double gamma, double* bh, hipStream_t st);
+
 // setup.hip
 int launch_setup(const float* S_dev, int L, int N, const double* C_dev /* L x L or NULL */,
                  double* Ci_dev /* L x L out, when C given */, double* W_dev /* L x N out */,

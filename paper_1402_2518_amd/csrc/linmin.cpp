@@ -196,6 +196,7 @@ void linmin_default_opts(linmin_opts* o) {
   o->iters = nullptr;
   o->objective = nullptr;
   o->stage_events = nullptr;
+  o->keep = nullptr;
 }
 
 const char* linmin_strerror(int code) {
@@ -387,6 +388,7 @@ int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigm
   rc = mark(0);
   if (rc == LINMIN_OK) rc = from_launch(lm::launch_gemm_proj_f64(cube, P, lib->L, lib->Wh, lib->ldw, lib->N, bh, c, st));
   if (rc == LINMIN_OK && lib->Ci) rc = from_launch(lm::launch_quadform_f64(cube, P, lib->L, lib->Ci, lib->L, c, st));
+  if (rc == LINMIN_OK && o.keep) rc = from_launch(lm::launch_keep(lib->N, P, o.keep, c, lib->gamma, bh, st));
   if (rc == LINMIN_OK) rc = mark(1);
   if (rc == LINMIN_OK) {
     lm::IpmParams prm = make_ipm(lib, P, sigma, out_coeffs, status, o.iters, o.objective, o, w, ws, want_cov);
@@ -488,6 +490,7 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   else linmin_default_opts(&o);
   int rc = check_opts(o);
   if (rc != LINMIN_OK) return rc;
+  if (o.keep) return LINMIN_EINVAL;  // per-pixel spectrum selection is for single calls
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return LINMIN_EHIP;
   for (int j = 0; j < n_jobs; ++j) {
@@ -658,3 +661,38 @@ int linmin_batch_destroy(linmin_batch b) {
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int linmin_error_maps(linmin_lib lib, int64_t P, const double* objective, const float* sigma, const double* cov,
+                      int cov_layout, double* rms, double* sigma1, void* stream) {
+  if (!lib || P < 0) return LINMIN_EINVAL;
+  if (P == 0) return LINMIN_OK;
+  if ((rms && !objective) || (sigma1 && !cov)) return LINMIN_EINVAL;
+  if (sigma1 && (cov_layout < LINMIN_COV_FULL || cov_layout > LINMIN_COV_DIAG)) return LINMIN_EINVAL;
+  return from_launch(lm::launch_error_maps(lib->N, P, lib->L, objective, sigma, cov, cov_layout, rms, sigma1,
+                                           static_cast<hipStream_t>(stream)));
+}
+
+int linmin_thresholds(int N, int64_t P, const double* coeffs, const uint8_t* present, double* thresholds,
+                      void* stream) {
+  if (N < 1 || N > LINMIN_N_MAX || P < 0 || !thresholds || (P > 0 && (!coeffs || !present))) return LINMIN_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, lm::thresholds_workspace_bytes(N, P), st) != hipSuccess) return LINMIN_ENOMEM;
+  int rc = from_launch(lm::launch_thresholds(N, P, coeffs, present, thresholds, ws, st));
+  if (hipFreeAsync(ws, st) != hipSuccess && rc == LINMIN_OK) rc = LINMIN_EHIP;
+  return rc;
+}
+
+int linmin_detect(int N, int64_t P, const double* coeffs, const double* sigma1, const double* rms,
+                  const double* thresholds, double rms_max, uint8_t* detected, void* stream) {
+  if (N < 1 || N > LINMIN_N_MAX || P < 0) return LINMIN_EINVAL;
+  if (P == 0) return LINMIN_OK;
+  if (!coeffs || !sigma1 || !rms || !thresholds || !detected) return LINMIN_EINVAL;
+  return from_launch(lm::launch_detect(N, P, coeffs, sigma1, rms, thresholds, rms_max, detected,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"
+

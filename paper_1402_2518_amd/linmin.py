@@ -25,7 +25,7 @@ N_MAX = 128
 EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linmin_workspace_bytes",
            "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror",
            "linmin_extra_spectra", "linmin_batch_create", "linmin_batch_run", "linmin_batch_device_bytes",
-           "linmin_batch_destroy")
+           "linmin_batch_destroy", "linmin_error_maps", "linmin_thresholds", "linmin_detect")
 
 
 class Opts(ctypes.Structure):
@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
                 ("tol_p", ctypes.c_double), ("eta", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("tau", ctypes.c_double), ("deg_tol", ctypes.c_double), ("mu_switch", ctypes.c_double),
                 ("status", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("objective", ctypes.c_void_p),
-                ("stage_events", ctypes.c_void_p)]
+                ("stage_events", ctypes.c_void_p), ("keep", ctypes.c_void_p)]
 
 
 class Job(ctypes.Structure):
@@ -86,6 +86,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.linmin_batch_device_bytes.restype = ctypes.c_size_t
         lib.linmin_batch_destroy.argtypes = [vp]
         lib.linmin_batch_destroy.restype = ctypes.c_int
+        i64, dbl = ctypes.c_int64, ctypes.c_double
+        lib.linmin_error_maps.argtypes = [vp, i64, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+        lib.linmin_error_maps.restype = ctypes.c_int
+        lib.linmin_thresholds.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
+        lib.linmin_thresholds.restype = ctypes.c_int
+        lib.linmin_detect.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, dbl, vp, vp]
+        lib.linmin_detect.restype = ctypes.c_int
         lib.linmin_strerror.argtypes = [ctypes.c_int]
         lib.linmin_strerror.restype = ctypes.c_char_p
         _lib = lib
@@ -173,11 +180,13 @@ class Library:
         return int(load().linmin_workspace_bytes(self._h, int(P), ctypes.byref(o)))
 
     def unmix_into(self, cube, sigma, out_a, out_cov=None, status=None, iters=None, objective=None,
-                   precision: str = "fp64", cov: str | None = "full", stream=None, events=None, **opts):
+                   precision: str = "fp64", cov: str | None = "full", stream=None, events=None, keep=None, **opts):
         """Enqueue one unmix on ``stream`` into caller-provided device tensors.
 
         ``events``: optional four ``torch.cuda.Event(enable_timing=True)``
         recorded before the projections, the solve, the covariance and after.
+        ``keep``: optional P x N uint8 device tensor, the spectra each pixel
+        keeps (second pass); the others are held at zero.
         """
         import torch
         if cube.dtype != torch.float32 or not cube.is_contiguous() or cube.dim() != 2:
@@ -213,6 +222,8 @@ class Library:
         o.status = None if status is None else status.data_ptr()
         o.iters = None if iters is None else iters.data_ptr()
         o.objective = None if objective is None else objective.data_ptr()
+        _check(keep, "keep", torch.uint8, P * N)
+        o.keep = None if keep is None else keep.data_ptr()
         if stream is None:
             stream = torch.cuda.current_stream()
         ev_arr = None
@@ -227,6 +238,22 @@ class Library:
                                  ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:
             raise LinminError(rc, "linmin_unmix")
+
+    def error_maps(self, objective, sigma, cov_out=None, cov: str = "full", stream=None):
+        """RMS map (P) from the objective of an unmix, and the 1-sigma error
+        map (P x N) from its covariance output (None: not computed)."""
+        import torch
+        P = objective.numel()
+        rms = torch.empty(P, dtype=torch.float64, device=objective.device)
+        s1 = None if cov_out is None else torch.empty((P, self.N), dtype=torch.float64, device=objective.device)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        rc = load().linmin_error_maps(self._h, int(P), _ptr(objective), _ptr(sigma), _ptr(cov_out),
+                                      _COV[cov] if cov_out is not None else 0, _ptr(rms), _ptr(s1),
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise LinminError(rc, "linmin_error_maps")
+        return rms, s1
 
     def unmix(self, cube, sigma=None, precision: str = "fp64", cov: str | None = "full",
               stream=None, **opts):
@@ -326,4 +353,40 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def thresholds(coeffs, present, stream=None):
+    """Thresholds of eq. 8 (N, float64 device tensor) from P x N coefficients
+    and a P x N uint8 mask of where each endmember is present."""
+    import torch
+    P, N = coeffs.shape
+    if present.dtype != torch.uint8 or present.shape != coeffs.shape or not present.is_contiguous():
+        raise ValueError("present must be a contiguous P x N uint8 tensor")
+    if coeffs.dtype != torch.float64 or not coeffs.is_contiguous():
+        raise ValueError("coeffs must be a contiguous float64 tensor")
+    out = torch.empty(N, dtype=torch.float64, device=coeffs.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = load().linmin_thresholds(int(N), int(P), _ptr(coeffs), _ptr(present), _ptr(out),
+                                  ctypes.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise LinminError(rc, "linmin_thresholds")
+    return out
+
+
+def detect(coeffs, sigma1, rms, thr, rms_max: float, stream=None):
+    """Detection rules of Sec. 4 as a P x N uint8 device tensor."""
+    import torch
+    P, N = coeffs.shape
+    for name, t, n in (("coeffs", coeffs, P * N), ("sigma1", sigma1, P * N), ("rms", rms, P), ("thr", thr, N)):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float64 tensor of {n} values")
+    out = torch.empty((P, N), dtype=torch.uint8, device=coeffs.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = load().linmin_detect(int(N), int(P), _ptr(coeffs), _ptr(sigma1), _ptr(rms), _ptr(thr), float(rms_max),
+                              _ptr(out), ctypes.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise LinminError(rc, "linmin_detect")
+    return out
 

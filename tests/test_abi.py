@@ -50,7 +50,7 @@ def test_constants_match_header():
 
 def test_opts_struct_layout():
     # field order and size of linmin_opts as declared in the header
-    assert ctypes.sizeof(linmin.Opts) == 5 * 4 + 4 + 8 * 8 + 4 * 8  # five ints, padding, doubles, pointers
+    assert ctypes.sizeof(linmin.Opts) == 5 * 4 + 4 + 8 * 8 + 5 * 8  # five ints, padding, doubles, pointers
 
 
 def test_strerror_and_defaults_without_gpu():
@@ -76,6 +76,16 @@ def test_strerror_and_defaults_without_gpu():
     assert lib.linmin_batch_run(None, None) == linmin.EINVAL
     assert lib.linmin_batch_destroy(None) == linmin.EINVAL
     assert lib.linmin_batch_device_bytes(None) == 0
+    keep_opts = linmin.default_opts()
+    keep_opts.keep = 16  # any non-NULL pointer: batches refuse the per-pixel selection before device work
+    assert lib.linmin_batch_create(None, 0, ctypes.byref(keep_opts), ctypes.byref(h)) == linmin.EINVAL
+    # detection entry points check their arguments first
+    assert lib.linmin_error_maps(None, 5, None, None, None, 1, None, None, None) == linmin.EINVAL
+    assert lib.linmin_thresholds(0, 5, None, None, None, None) == linmin.EINVAL
+    assert lib.linmin_thresholds(4, 5, None, None, None, None) == linmin.EINVAL
+    assert lib.linmin_detect(129, 5, None, None, None, None, 1.0, None, None) == linmin.EINVAL
+    assert lib.linmin_detect(4, 5, None, None, None, None, 1.0, None, None) == linmin.EINVAL
+    assert lib.linmin_detect(4, 0, None, None, None, None, 1.0, None, None) == linmin.OK
 
 
 def test_job_struct_layout():

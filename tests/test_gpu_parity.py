@@ -514,3 +514,99 @@ def test_serving_mix_identical_alone(dev):
     _say(f"  {summary}")
     for lib in libs.values():
         lib.close()
+
+
+def test_detection_kernels_on_synthetic_arrays(dev):
+    """Thresholds (eq. 8) and detection rules on the same seeded arrays on
+    both sides: thresholds to reduction-order rounding, decisions exactly."""
+    from paper_1402_2518_amd import linmin
+    _say("[gpu] detection kernels on seeded arrays")
+    rng = np.random.default_rng(61)
+    P, N = 20_011, 37
+    present = rng.random((P, N)) < 0.25
+    present[:, 5] = True                      # never absent: NaN threshold
+    A = np.where(present, rng.uniform(0.02, 0.6, (P, N)), np.abs(0.003 * rng.standard_normal((P, N))))
+    thr_o = oracle.thresholds(A, present)
+    At = torch.from_numpy(A).to(dev)
+    thr_g = linmin.thresholds(At, torch.from_numpy(present.astype(np.uint8)).to(dev)).cpu().numpy()
+    assert np.isnan(thr_g[5]) and np.isnan(thr_o[5])
+    ok = ~np.isnan(thr_o)
+    assert np.abs(thr_g[ok] - thr_o[ok]).max() <= 1e-13 * np.abs(thr_o[ok]).max()
+    s1 = np.abs(0.05 * rng.standard_normal((P, N)))
+    rms = rng.uniform(0.0, 0.02, P)
+    thr = rng.uniform(0.01, 0.1, N)
+    d_o = oracle.detect(A, s1, rms, thr, rms_max=0.012)
+    d_g = linmin.detect(At, torch.from_numpy(s1).to(dev), torch.from_numpy(rms).to(dev),
+                        torch.from_numpy(thr).to(dev), 0.012).cpu().numpy()
+    assert np.array_equal(d_g.astype(bool), d_o) and 0.05 < d_o.mean() < 0.5
+
+
+def test_detection_pipeline_against_the_oracle(dev):
+    """Unmix, RMS and 1-sigma maps, thresholds from the true presence, and
+    detection, each side from its own coefficients: maps to the unmixing
+    tolerances, thresholds to 1e-9, decisions equal except at near-ties."""
+    from paper_1402_2518_amd import linmin
+    _say("[gpu] detection pipeline")
+    w = synth.custom_workload(12, 96, 3000, seed=12)
+    S = synth.make_library(w)
+    X, s, Atrue = synth.make_cube(w, with_truth=True)
+    present = Atrue > 0
+    r = oracle.unmix(S, X, s)
+    rms_o, s1_o = oracle.rms_map(S, X, r["a"]), oracle.sigma1_map(r["cov"])
+    thr_o = oracle.thresholds(r["a"], present)
+    lib = linmin.Library(S)
+    Xd, sd = torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev)
+    g = lib.unmix(Xd, sd, cov="full")
+    rms_g, s1_g = lib.error_maps(g["objective"], sd, g["cov"], cov="full")
+    pres_t = torch.from_numpy(present.astype(np.uint8)).to(dev)
+    thr_g = linmin.thresholds(g["a"], pres_t)
+    rms_max = float(np.percentile(rms_o, 90))
+    det_g = linmin.detect(g["a"], s1_g, rms_g, thr_g, rms_max).cpu().numpy().astype(bool)
+    det_o = oracle.detect(r["a"], s1_o, rms_o, thr_o, rms_max)
+    ok = (g["status"].cpu().numpy() == 0) & (r["status"] == 0)
+    rms_h, s1_h = rms_g.cpu().numpy(), s1_g.cpu().numpy()
+    assert np.abs(rms_h / rms_o - 1).max() <= 1e-8
+    scale = np.maximum(s1_o[ok].max(1, keepdims=True), s[ok, None] / np.sqrt(lib.gamma))
+    assert (np.abs(s1_h[ok] - s1_o[ok]) / scale).max() <= 1e-6
+    thr_h = thr_g.cpu().numpy()
+    fin = ~np.isnan(thr_o)   # the extras are present everywhere: no threshold
+    assert np.array_equal(np.isnan(thr_h), ~fin) and fin.sum() == 8
+    assert np.abs(thr_h[fin] - thr_o[fin]).max() <= 1e-9
+    a_o, thr = r["a"], thr_o[None, :]
+    near = (np.abs(a_o - thr) <= 1e-6) | (np.abs(s1_o - a_o) <= 1e-6 * np.maximum(a_o, 1e-12)) | \
+           (np.abs(rms_o - rms_max)[:, None] <= 1e-8 * rms_max)
+    assert ((det_g == det_o) | near).all() and det_o.sum() > 0
+    lib.close()
+
+
+@pytest.mark.parametrize("constraint", ["sto", "pos"])
+def test_second_pass_against_the_oracle(dev, constraint):
+    """Second pass: each pixel unmixed again with a subset of the spectra
+    (about half, some pixels one or two, one pixel none) against the
+    oracle's unmix of each pixel's sub-library."""
+    from paper_1402_2518_amd import linmin
+    _say(f"[gpu] second pass {constraint}")
+    w = synth.custom_workload(16, 96, 300, seed=16)
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    rng = np.random.default_rng(5)
+    keep = rng.random((300, 16)) < 0.5
+    keep[:20] = False
+    keep[:10, 3] = True                            # one spectrum
+    keep[10:20, 1] = keep[10:20, 7] = True         # two spectra
+    keep[20] = False                               # none: reported non-finite
+    code = {"sto": oracle.STO, "pos": oracle.POS}[constraint]
+    r = oracle.second_pass(S, X, s, keep, constraint=code)
+    lib = linmin.Library(S)
+    g = lib.unmix(torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev), cov="full", constraint=constraint,
+                  keep=torch.from_numpy(keep.astype(np.uint8)).to(dev))
+    ga, gst = g["a"].cpu().numpy(), g["status"].cpu().numpy()
+    assert gst[20] & oracle.NONFINITE and np.isnan(ga[20]).all()
+    rows = np.arange(300) != 20
+    assert np.abs(ga[rows] - r["a"][rows]).max() <= 1e-6
+    assert (ga[rows][~keep[rows]] == 0).all()
+    ok = rows & (gst == 0) & (r["status"] == 0)
+    assert ok.mean() > 0.9
+    assert _cov_rel_err({"cov": g["cov"].cpu().numpy(), "sigma": s.astype(float), "gamma": lib.gamma},
+                        {"cov": r["cov"]}, ok) <= 1e-6
+    lib.close()
