@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6e12          # MI355X FP64, dense matrix cores and vector units alike, FLOP/s
 PEAK_HBM = 8.0e12            # bytes/s
 PROFILE = os.path.join(ROOT, "profiles", "orbital_N36_L240_kernels.md")
-IPM_KERNEL = "lm::ipm_tile_kernel<9, 0, 0>"
+IPM_KERNEL = "lm::ipm_tile_kernel<9, 0, 0, false>"
 IPM_SOURCES = ("paper_1402_2518_amd/csrc/ipm_tile.hip", "paper_1402_2518_amd/csrc/common.h",
                "paper_1402_2518_amd/csrc/kernels.h")
 
