@@ -610,3 +610,43 @@ def test_second_pass_against_the_oracle(dev, constraint):
     assert _cov_rel_err({"cov": g["cov"].cpu().numpy(), "sigma": s.astype(float), "gamma": lib.gamma},
                         {"cov": r["cov"]}, ok) <= 1e-6
     lib.close()
+
+
+def test_batch_run_in_a_graph(dev):
+    """A planned batch enqueues kernels only, so one run can be captured in a
+    HIP graph; every replay (with eager work and synchronisation between
+    them) reproduces the eager run bit for bit."""
+    from paper_1402_2518_amd import linmin
+    _say("[gpu] batch run captured in a graph")
+    data = [_batch_item(N, L, P, seed=800 + i) for i, (N, L, P) in
+            enumerate([(8, 64, 700), (36, 240, 1500), (48, 128, 333), (96, 128, 200)])]
+    libs, items = [], []
+    for S, X, s in data:
+        lib = linmin.Library(S)
+        libs.append(lib)
+        items.append((lib, torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev)))
+    b = linmin.Batch(items, precision="mixed", cov="packed")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b.run(side)
+    torch.cuda.synchronize()
+    ref = [{k: v.clone() for k, v in r.items() if v is not None} for r in b.results]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        b.run(side)
+    for rep in range(3):
+        for r in b.results:
+            for t in r.values():
+                if t is not None:
+                    t.fill_(9)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = items[0][1].sum().item()  # eager work between replays
+        for i, (r, want) in enumerate(zip(b.results, ref)):
+            for k, v in want.items():
+                assert torch.equal(r[k].nan_to_num(3.5), v.nan_to_num(3.5)), (rep, i, k)
+    del g
+    b.close()
+    for lib in libs:
+        lib.close()
