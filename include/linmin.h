@@ -82,7 +82,7 @@ typedef struct linmin_lib_s *linmin_lib;
 typedef struct {
     int precision;      /* LINMIN_FP64 or LINMIN_MIXED */
     int cov_layout;     /* LINMIN_COV_* */
-    int maxit;          /* interior-point iteration cap (default 100) */
+    int maxit;          /* interior-point iteration cap (default 200) */
     int max_polish;     /* partition corrections in the finishing step (16) */
     int constraint;     /* LINMIN_STO (default), LINMIN_SLO or LINMIN_POS.  With
                            SLO the slack of 1^T a <= 1 and the sum multiplier
@@ -253,15 +253,15 @@ int linmin_batch_destroy(linmin_batch batch);
  * Detection post-processing (Sec. 3.1 and 4).  All pointers are device
  * memory; every call is asynchronous on stream (NULL: default stream).
  *
- * linmin_error_maps: per pixel the RMS of the fit, rms_p = s_p sqrt(F_p / L)
- * (the root mean square over the L channels of the residual in the
- * renormalised space of Sec. 2.3, from the objective F of linmin_unmix and
- * sigma as given to it), and per coefficient the 1-sigma error, the square
- * root of the covariance diagonal (cov in cov_layout as written by
- * linmin_unmix).  rms (P) or sigma1 (P x N) may be NULL to skip it; NaN
- * inputs give NaN.  Errors: EINVAL.
+ * linmin_error_maps: per pixel the RMS of the fit, the root mean square over
+ * the L channels of the residual y - a S in reflectance units (Sec. 3.1;
+ * not whitened by a noise covariance), from the cube (P x L float32) and
+ * the coefficients (P x N) of linmin_unmix; and per coefficient the 1-sigma
+ * error, the square root of the covariance diagonal (cov in cov_layout as
+ * written by linmin_unmix).  rms (P) or sigma1 (P x N) may be NULL to skip
+ * it; NaN inputs give NaN.  Errors: EINVAL.
  */
-int linmin_error_maps(linmin_lib lib, int64_t P, const double *objective, const float *sigma, const double *cov,
+int linmin_error_maps(linmin_lib lib, int64_t P, const float *cube, const double *coeffs, const double *cov,
                       int cov_layout, double *rms, double *sigma1, void *stream);
 
 /*

@@ -173,15 +173,11 @@ def extra_spectra(L: int, n: int = 4, wavelengths: np.ndarray | None = None) -> 
 # ---------------------------------------------------------------------------
 # Detection post-processing (Sec. 3.1 eq. 8 and the rules of Sec. 4)
 # ---------------------------------------------------------------------------
-def rms_map(S: np.ndarray, X: np.ndarray, A: np.ndarray, C: np.ndarray | None = None) -> np.ndarray:
-    """Root-mean-square of each pixel's fit residual over its L channels, in
-    the renormalised space of Sec. 2.3: with C^{-1} = Lc Lc^T the residual is
-    (x - a S) Lc; for C = I the plain reflectance residual."""
+def rms_map(S: np.ndarray, X: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """Root-mean-square of each pixel's fit residual y - a S over its L
+    channels, in reflectance units (not whitened by a noise covariance)."""
     Sd, Xd = np.asarray(S, np.float64), np.asarray(X, np.float64)
     R = Xd - np.asarray(A, np.float64) @ Sd
-    if C is not None:
-        Lc = np.linalg.cholesky(np.linalg.inv(np.asarray(C, np.float64)))
-        R = R @ Lc
     return np.sqrt((R * R).sum(1) / Sd.shape[1])
 
 

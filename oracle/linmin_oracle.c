@@ -79,7 +79,7 @@ typedef struct {
 
 void lo_default_opts(lo_opts *o)
 {
-    o->maxit = 100;
+    o->maxit = 200;
     o->max_polish = 16;
     o->tol_mu = 1e-13;
     o->tol_d = 1e-12;

@@ -1,9 +1,10 @@
 // detect.hip -- detection post-processing of unmixing results and the
 // restriction of a pixel to chosen spectra (second pass).
 //
-//   * RMS of each pixel's fit in the renormalised space of Sec. 2.3:
-//     F_p s_p^2 is the squared residual norm (eq. 6), so
-//     rms_p = s_p sqrt(F_p / L);
+//   * RMS of each pixel's fit, the root mean square over the L channels of
+//     the residual y - a S in reflectance units (Sec. 3.1), computed from the
+//     residual itself: a pixel per 16-lane group, its coefficients staged in
+//     LDS, the library read through the L2 cache;
 //   * 1-sigma error of each coefficient: square root of the covariance
 //     diagonal (end of Sec. 2.3);
 //   * the threshold of eq. 8 per endmember from coefficients of pixels where
@@ -21,26 +22,41 @@
 
 namespace lm {
 
-__global__ __launch_bounds__(256) void error_maps_kernel(int n, int64_t P, int L, const double* __restrict__ objective,
-                                                         const float* __restrict__ sigma,
-                                                         const double* __restrict__ cov, int layout,
-                                                         double* __restrict__ rms, double* __restrict__ sigma1) {
+__global__ __launch_bounds__(256) void sigma1_kernel(int n, int64_t P, const double* __restrict__ cov, int layout,
+                                                     double* __restrict__ sigma1) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P * n) return;
   const int64_t p = t / n;
   const int i = (int)(t - p * n);
-  if (sigma1) {
-    double v;
-    if (layout == 1) v = cov[p * n * n + (int64_t)i * n + i];
-    else if (layout == 2) v = cov[p * ((int64_t)n * (n + 1) / 2) + (int64_t)i * (i + 1) / 2 + i];
-    else v = cov[p * n + i];
-    sigma1[t] = v != v ? v : sqrt(fmax(v, 0.0));
+  double v;
+  if (layout == 1) v = cov[p * n * n + (int64_t)i * n + i];
+  else if (layout == 2) v = cov[p * ((int64_t)n * (n + 1) / 2) + (int64_t)i * (i + 1) / 2 + i];
+  else v = cov[p * n + i];
+  sigma1[t] = v != v ? v : sqrt(fmax(v, 0.0));
+}
+
+// 16 pixels per workgroup, one per 16-lane group; lane t takes channels
+// t, t + 16, ...
+__global__ __launch_bounds__(256) void rms_kernel(int n, int64_t P, int L, const float* __restrict__ Y,
+                                                  const double* __restrict__ A, const float* __restrict__ S,
+                                                  double* __restrict__ rms) {
+  __shared__ double sa[16][128];
+  const int g = threadIdx.x >> 4, t = threadIdx.x & 15;
+  const int64_t p = (int64_t)blockIdx.x * 16 + g;
+  const bool live = p < P;
+  for (int i = t; i < n; i += 16) sa[g][i] = live ? A[p * n + i] : 0.0;
+  __syncthreads();
+  double acc = 0.0;
+  if (live) {
+    const float* y = Y + p * (int64_t)L;
+    for (int l = t; l < L; l += 16) {
+      double r = (double)y[l];
+      for (int i = 0; i < n; ++i) r = fmaT(-sa[g][i], (double)S[(int64_t)i * L + l], r);
+      acc = fmaT(r, r, acc);
+    }
   }
-  if (rms && i == 0) {
-    const double s = sigma ? (double)sigma[p] : 1.0;
-    const double F = objective[p];
-    rms[p] = F != F ? F : s * sqrt(fmax(F, 0.0) / L);
-  }
+  acc = gsum<16>(acc);
+  if (live && t == 0) rms[p] = sqrt(acc / L);
 }
 
 // Per-column partial sums over a workgroup's rows: class 0 = present,
@@ -144,12 +160,16 @@ __global__ __launch_bounds__(256) void keep_kernel(int n, int64_t P, const uint8
     if (!keep[p * n + i]) bh[p * n + i] = kept ? -M : __builtin_nan("");
 }
 
-int launch_error_maps(int n, int64_t P, int L, const double* objective, const float* sigma, const double* cov,
+int launch_error_maps(int n, int64_t P, int L, const float* Y, const double* A, const float* S, const double* cov,
                       int layout, double* rms, double* sigma1, hipStream_t st) {
   if (P <= 0) return 0;
-  const int64_t total = P * n;
-  hipLaunchKernelGGL(error_maps_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, P, L, objective,
-                     sigma, cov, layout, rms, sigma1);
+  if (n > 128) return -1;
+  if (sigma1) {
+    const int64_t total = P * n;
+    hipLaunchKernelGGL(sigma1_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, P, cov, layout,
+                       sigma1);
+  }
+  if (rms) hipLaunchKernelGGL(rms_kernel, dim3((unsigned)((P + 15) / 16)), dim3(256), 0, st, n, P, L, Y, A, S, rms);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

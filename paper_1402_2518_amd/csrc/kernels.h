@@ -139,7 +139,7 @@ int launch_cov(int n, int64_t P, const double* Gh, int ldg, const double* dcov, 
                double* out_cov, uint8_t* big, hipStream_t st);
 
 // detect.hip
-int launch_error_maps(int n, int64_t P, int L, const double* objective, const float* sigma, const double* cov,
+int launch_error_maps(int n, int64_t P, int L, const float* Y, const double* A, const float* S, const double* cov,
                       int layout, double* rms, double* sigma1, hipStream_t st);
 size_t thresholds_workspace_bytes(int n, int64_t P);
 int launch_thresholds(int n, int64_t P, const double* A, const uint8_t* present, double* thr, double* ws,

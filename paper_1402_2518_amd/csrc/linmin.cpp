@@ -28,6 +28,7 @@ struct linmin_lib_s {
   float* Gh32;   // NC x NC
   double* G;     // N x N, unscaled Gram
   double* Ci;    // L x L inverse noise covariance, or NULL for C = I
+  float* S;      // N x L library as given (the residual of the RMS map)
 };
 
 namespace {
@@ -57,6 +58,7 @@ void free_lib(linmin_lib l) {
   (void)hipFree(l->Gh32);
   (void)hipFree(l->G);
   (void)hipFree(l->Ci);
+  (void)hipFree(l->S);
   delete l;
 }
 
@@ -181,7 +183,7 @@ void linmin_default_opts(linmin_opts* o) {
   if (!o) return;
   o->precision = LINMIN_FP64;
   o->cov_layout = LINMIN_COV_FULL;
-  o->maxit = 100;
+  o->maxit = 200;
   o->max_polish = 16;
   o->constraint = LINMIN_STO;
   o->tol_mu = 1e-13;
@@ -303,7 +305,7 @@ int linmin_create_library(const float* S, int L, int N, const double* noise_cov,
     TRY(hip_ok(hipMemcpy(Gh.data(), lib->G, sizeof(double) * Gh.size(), hipMemcpyDeviceToHost)));
     lib->stable = nearly_singular(Gh.data(), N, lib->gamma, kNearlySingular) ? 1 : 0;
   }
-  (void)hipFree(dS);
+  lib->S = dS;  // kept for the RMS map
   (void)hipFree(dC);
   (void)hipFree(dW);
   (void)hipFree(dgam);
@@ -664,13 +666,13 @@ int linmin_batch_destroy(linmin_batch b) {
 
 extern "C" {
 
-int linmin_error_maps(linmin_lib lib, int64_t P, const double* objective, const float* sigma, const double* cov,
+int linmin_error_maps(linmin_lib lib, int64_t P, const float* cube, const double* coeffs, const double* cov,
                       int cov_layout, double* rms, double* sigma1, void* stream) {
   if (!lib || P < 0) return LINMIN_EINVAL;
   if (P == 0) return LINMIN_OK;
-  if ((rms && !objective) || (sigma1 && !cov)) return LINMIN_EINVAL;
+  if ((rms && (!cube || !coeffs)) || (sigma1 && !cov)) return LINMIN_EINVAL;
   if (sigma1 && (cov_layout < LINMIN_COV_FULL || cov_layout > LINMIN_COV_DIAG)) return LINMIN_EINVAL;
-  return from_launch(lm::launch_error_maps(lib->N, P, lib->L, objective, sigma, cov, cov_layout, rms, sigma1,
+  return from_launch(lm::launch_error_maps(lib->N, P, lib->L, cube, coeffs, lib->S, cov, cov_layout, rms, sigma1,
                                            static_cast<hipStream_t>(stream)));
 }
 

@@ -239,16 +239,17 @@ class Library:
         if rc != OK:
             raise LinminError(rc, "linmin_unmix")
 
-    def error_maps(self, objective, sigma, cov_out=None, cov: str = "full", stream=None):
-        """RMS map (P) from the objective of an unmix, and the 1-sigma error
-        map (P x N) from its covariance output (None: not computed)."""
+    def error_maps(self, cube, coeffs, cov_out=None, cov: str = "full", stream=None):
+        """RMS map (P) of the fit residual y - a S in reflectance units, and
+        the 1-sigma error map (P x N) from a covariance output (None: not
+        computed)."""
         import torch
-        P = objective.numel()
-        rms = torch.empty(P, dtype=torch.float64, device=objective.device)
-        s1 = None if cov_out is None else torch.empty((P, self.N), dtype=torch.float64, device=objective.device)
+        P = coeffs.shape[0]
+        rms = torch.empty(P, dtype=torch.float64, device=coeffs.device)
+        s1 = None if cov_out is None else torch.empty((P, self.N), dtype=torch.float64, device=coeffs.device)
         if stream is None:
             stream = torch.cuda.current_stream()
-        rc = load().linmin_error_maps(self._h, int(P), _ptr(objective), _ptr(sigma), _ptr(cov_out),
+        rc = load().linmin_error_maps(self._h, int(P), _ptr(cube), _ptr(coeffs), _ptr(cov_out),
                                       _COV[cov] if cov_out is not None else 0, _ptr(rms), _ptr(s1),
                                       ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:

@@ -557,7 +557,7 @@ def test_detection_pipeline_against_the_oracle(dev):
     lib = linmin.Library(S)
     Xd, sd = torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev)
     g = lib.unmix(Xd, sd, cov="full")
-    rms_g, s1_g = lib.error_maps(g["objective"], sd, g["cov"], cov="full")
+    rms_g, s1_g = lib.error_maps(Xd, g["a"], g["cov"], cov="full")
     pres_t = torch.from_numpy(present.astype(np.uint8)).to(dev)
     thr_g = linmin.thresholds(g["a"], pres_t)
     rms_max = float(np.percentile(rms_o, 90))
@@ -577,6 +577,19 @@ def test_detection_pipeline_against_the_oracle(dev):
            (np.abs(rms_o - rms_max)[:, None] <= 1e-8 * rms_max)
     assert ((det_g == det_o) | near).all() and det_o.sum() > 0
     lib.close()
+    # with a noise covariance the RMS stays the plain reflectance residual
+    rng = np.random.default_rng(23)
+    Sn = synth.mineral_spectra(10, 80, rng).astype(np.float32)
+    Q = rng.standard_normal((80, 80))
+    C = (Q @ Q.T / 80 + np.diag(rng.uniform(0.5, 2.0, 80))) * 1e-4
+    Xn = (rng.dirichlet(np.ones(10), 400) @ Sn.astype(float) + 0.01 * rng.standard_normal((400, 80))).astype(np.float32)
+    rn = oracle.unmix(Sn, Xn, None, C=C, cov=False)
+    libn = linmin.Library(Sn, C)
+    Xnd = torch.from_numpy(Xn).to(dev)
+    gn = libn.unmix(Xnd, None, cov=None)
+    rms_n, _ = libn.error_maps(Xnd, gn["a"])
+    assert np.abs(rms_n.cpu().numpy() / oracle.rms_map(Sn, Xn, rn["a"]) - 1).max() <= 1e-8
+    libn.close()
 
 
 @pytest.mark.parametrize("constraint", ["sto", "pos"])

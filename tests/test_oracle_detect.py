@@ -28,14 +28,23 @@ def test_rms_matches_the_reported_objective():
     assert np.abs(rms ** 2 * S.shape[1] / (r["F"] * s.astype(float) ** 2) - 1).max() <= 1e-8
 
 
-def test_rms_with_noise_covariance():
+def test_rms_with_noise_covariance_is_unwhitened():
+    # with a noise covariance the map stays in reflectance units: it equals
+    # the expanded form y.y - 2 a.(S y) + a.(S S^T) a of the plain residual,
+    # and does not change when C is scaled (the coefficients do not)
     rng = np.random.default_rng(8)
     S, X, s = _cube(N=6, L=40, P=30, seed=8)
     Q = rng.standard_normal((40, 40))
     C = Q @ Q.T / 40 + np.diag(rng.uniform(0.5, 2.0, 40))
     r = oracle.unmix(S, X, s, C=C, cov=False)
-    rms = oracle.rms_map(S, X, r["a"], C=C)
-    assert np.abs(rms ** 2 * 40 / (r["F"] * s.astype(float) ** 2) - 1).max() <= 1e-8
+    rms = oracle.rms_map(S, X, r["a"])
+    Sd, Xd, a = S.astype(float), X.astype(float), r["a"]
+    sq = (Xd * Xd).sum(1) - 2 * ((Xd @ Sd.T) * a).sum(1) + ((a @ (Sd @ Sd.T)) * a).sum(1)
+    assert np.abs(rms ** 2 * 40 / sq - 1).max() <= 1e-8
+    r2 = oracle.unmix(S, X, s, C=7.0 * C, cov=False)
+    assert np.abs(oracle.rms_map(S, X, r2["a"]) / rms - 1).max() <= 1e-9
+    # and differs from the whitened residual norm (F s^2) when C != I
+    assert np.abs(rms ** 2 * 40 / (r["F"] * s.astype(float) ** 2) - 1).max() > 1e-3
 
 
 def test_rms_of_an_exact_mixture_is_zero():
