@@ -114,10 +114,10 @@ def test_workload_samples_parity(dev, name, n, precision):
     _say(f"[gpu]   iters gpu mean {g['iters'].mean():.2f} oracle {r['iters'].mean():.2f}")
 
 
-@pytest.mark.parametrize("N", [1, 2, 5, 16, 24, 31, 40, 48, 57, 64, 80, 96])
+@pytest.mark.parametrize("N", [1, 2, 5, 16, 24, 31, 40, 48, 57, 64, 80, 96, 100, 128])
 def test_library_sizes(dev, N):
     _say(f"[gpu] library size N={N}")
-    w = synth.custom_workload(N, max(N, 96) if N <= 64 else 128, 517, seed=N, n_extra=min(4, N - 1) if N > 1 else 0,
+    w = synth.custom_workload(N, max(N, 96) if N <= 64 else (128 if N <= 96 else 160), 517, seed=N, n_extra=min(4, N - 1) if N > 1 else 0,
                               k_max=max(1, min(4, N - 4)) if N > 4 else 1)
     S = synth.make_library(w)
     X, s = synth.make_cube(w)
