@@ -7,6 +7,7 @@ the design doc): coefficients 1e-6 absolute for FP64 and 1e-3 for the mixed form
 1e-6 relative to its largest entry on certified non-degenerate pixels;
 objective 1e-9 relative (FP64) / 1e-4 relative (mixed).
 """
+import os
 import sys
 
 import numpy as np
@@ -660,6 +661,78 @@ def test_batch_run_in_a_graph(dev):
             for k, v in want.items():
                 assert torch.equal(r[k].nan_to_num(3.5), v.nan_to_num(3.5)), (rep, i, k)
     del g
+    b.close()
+    for lib in libs:
+        lib.close()
+
+
+_VALU_CHECK = r"""
+import os, sys
+sys.path.insert(0, os.getcwd())
+sys.path.insert(0, os.path.join(os.getcwd(), "tests"))
+import numpy as np, torch
+import oracle
+from paper_1402_2518_amd import linmin, synth
+worst = 0.0
+for N, L in ((8, 64), (36, 240), (48, 128), (64, 128)):
+    w = synth.custom_workload(N, L, 600, seed=950 + N)
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    lib = linmin.Library(S)
+    g = lib.unmix(torch.from_numpy(X).to("cuda:0"), torch.from_numpy(s).to("cuda:0"), cov="full")
+    torch.cuda.synchronize()
+    r = oracle.unmix(S, X, s)
+    ok = (g["status"].cpu().numpy() == 0) & (r["status"] == 0)
+    assert ok.mean() > 0.95, (N, ok.mean())
+    worst = max(worst, float(np.abs(g["a"].cpu().numpy() - r["a"]).max()))
+    cg, cr = g["cov"].cpu().numpy()[ok], r["cov"][ok]
+    scale = np.maximum(np.abs(cr).reshape(len(cr), -1).max(1), s[ok].astype(float) ** 2 / lib.gamma)[:, None, None]
+    assert (np.abs(cg - cr) / scale).max() <= 1e-6, N
+    lib.close()
+print("worst", worst)
+assert worst <= 1e-6
+"""
+
+
+def test_lane_group_fp64_kernel_at_tile_sizes(dev):
+    """The lane-group FP64 kernel is complete for every N (the tile kernel
+    takes N <= 64 by default); run it in a child process with the tile
+    kernel switched off and check it against the oracle."""
+    import subprocess
+    _say("[gpu] lane-group FP64 kernel at N = 8..64 (child process)")
+    env = dict(os.environ, LINMIN_FP64_KERNEL="valu")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _VALU_CHECK], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+
+
+@pytest.mark.parametrize("constraint", ["sto", "slo"])
+def test_batch_mixes_factorisations_and_constraints(dev, constraint):
+    """One batch holding a well-conditioned library (explicit-inverse tile
+    factorisation), the paper's additional spectra placed first (stable
+    factorisation, same N), and a lane-group size, under a non-default
+    constraint option: each cube equals its single call bit for bit."""
+    from paper_1402_2518_amd import linmin
+    _say(f"[gpu] batch with both factorisations, {constraint}")
+    w = synth.WORKLOADS["orbital"]
+    S1 = synth.make_library(w)
+    S2 = np.concatenate([linmin.extra_spectra(w.L, 12), synth.make_library(w)[:24]])
+    X, s = synth.make_cube(w, p1=900)
+    S3, X3, s3 = _batch_item(80, 240, 300, seed=990)
+    items, libs = [], []
+    for S, XX, ss in ((S1, X, s), (S2, X, s), (S3, X3, s3)):
+        lib = linmin.Library(S)
+        libs.append(lib)
+        items.append((lib, torch.from_numpy(XX).to(dev), torch.from_numpy(ss).to(dev)))
+    b = linmin.Batch(items, precision="fp64", cov="full", constraint=constraint)
+    b.run()
+    torch.cuda.synchronize()
+    for i, ((lib, Xd, sd), r) in enumerate(zip(items, b.results)):
+        one = lib.unmix(Xd, sd, cov="full", constraint=constraint)
+        torch.cuda.synchronize()
+        for k in ("a", "cov", "status", "iters", "objective"):
+            assert torch.equal(r[k].nan_to_num(3.5), one[k].nan_to_num(3.5)), (i, k)
     b.close()
     for lib in libs:
         lib.close()
