@@ -131,7 +131,7 @@ def batch_leg(args, dev, stream):
     return out
 
 
-def serve_leg(args, dev):
+def serve_leg(args, dev, rate=None, seconds=None):
     """Poisson arrivals of cubes of 8 resident libraries through the request
     loop: latency under load, and sampled requests checked against the same
     request served alone and against the oracle."""
@@ -151,7 +151,9 @@ def serve_leg(args, dev):
         host[k] = S
         libs[k].unmix(pools[k][0][:64], pools[k][1][:64], cov="full")  # loads the kernels
     torch.cuda.synchronize()
-    t = serve.poisson_arrivals(args.serve_rate, args.serve_seconds, rng)
+    rate = args.serve_rate if rate is None else rate
+    seconds = args.serve_seconds if seconds is None else seconds
+    t = serve.poisson_arrivals(rate, seconds, rng)
     sample = set(rng.choice(len(t), size=min(12, len(t)), replace=False).tolist())
     reqs = []
     for rid, ta in enumerate(t):
@@ -162,11 +164,11 @@ def serve_leg(args, dev):
         r = serve.Request(rid, k, X[off:off + P], s[off:off + P], float(ta), keep=rid in sample)
         reqs.append(r)
     srv = serve.Server(libs, streams=4, slots=8, hbm_budget=96 << 30, precision="fp64", cov="full")
-    print(f"# serving: {len(reqs)} requests over {args.serve_seconds:.0f}s", file=sys.stderr, flush=True)
+    print(f"# serving: {len(reqs)} requests over {seconds:.0f}s", file=sys.stderr, flush=True)
     done = srv.run(reqs)
     torch.cuda.synchronize()
     out = serve.latency_summary(done)
-    out.update({"offered_rate_per_s": args.serve_rate, "seconds": args.serve_seconds, "libraries": 8,
+    out.update({"offered_rate_per_s": rate, "seconds": seconds, "libraries": 8,
                 "libraries_NL": [[libs[k].N, libs[k].L] for k in range(8)], "cov_layout": "full",
                 "precision": "fp64", "slots": srv.slots, "streams": len(srv.streams),
                 "hbm_budget_bytes": srv.budget, "max_running": srv.stats["max_running"],
@@ -210,6 +212,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson arrival stream of the serving leg (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="cubes per second arriving")
+    ap.add_argument("--serve-light-rate", type=float, default=25.0,
+                    help="a second, lighter stream (20 s) to show latency below saturation (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -352,6 +356,9 @@ def main():
     if args.serve_seconds > 0:
         torch.cuda.empty_cache()
         result["serving"] = serve_leg(args, dev)
+        if args.serve_light_rate > 0:
+            torch.cuda.empty_cache()
+            result["serving_light"] = serve_leg(args, dev, rate=args.serve_light_rate, seconds=20.0)
 
     if not args.no_cpu:
         oracle.build(force=False)
