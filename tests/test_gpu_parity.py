@@ -736,3 +736,29 @@ def test_batch_mixes_factorisations_and_constraints(dev, constraint):
     b.close()
     for lib in libs:
         lib.close()
+
+
+@pytest.mark.parametrize("name", ["orbital", "precision"])
+def test_full_size_launch_sampled(dev, name):
+    """The whole cube in one call, as the benchmark times it (orbital:
+    524,288 pixels at N = 36; precision: 307,200 at N = 64, L = 438), FP64
+    with full covariance; 512 pixels spread over the cube (both ends and the
+    last, ragged chunk included) against the oracle."""
+    from paper_1402_2518_amd import linmin
+    w = synth.WORKLOADS[name]
+    _say(f"[gpu] full-size launch {name} P={w.P}")
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    lib = linmin.Library(S)
+    g = lib.unmix(torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev), precision="fp64", cov="full")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([np.arange(8), np.arange(w.P - 8, w.P), rng.choice(w.P, 496, replace=False)]))
+    it = torch.from_numpy(idx).to(dev)
+    gs = {"a": g["a"][it].cpu().numpy(), "cov": g["cov"][it].cpu().numpy(), "status": g["status"][it].cpu().numpy(),
+          "iters": g["iters"][it].cpu().numpy(), "objective": g["objective"][it].cpu().numpy(),
+          "gamma": lib.gamma, "sigma": s[idx].astype(float)}
+    r = oracle.unmix(S, X[idx], s[idx])
+    _compare(gs, r)
+    assert int((g["status"] != 0).sum()) <= 0.01 * w.P
+    lib.close()
