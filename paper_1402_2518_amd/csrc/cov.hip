@@ -123,23 +123,32 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
       const double akk = rowbcast<kt>(R[kh][k]);
       if (!(akk != 0.0) || akk != akk) singular = true;
       const double r = 1.0 / akk;
-      double f[H];
+      // row update R_j <- al R_j + be K_kj: the pivot row is scaled by 1/akk
+      // (al = r, be = 0), every other row loses f = R_k / akk times the pivot
+      // row (al = 1, be = -f); the pivot column becomes f (-r on the pivot)
+      double al[H], be[H];
       static_for<0, H>([&](auto hh) {
         constexpr int h = decltype(hh)::value;
-        f[h] = R[h][k] * r;
+        const bool prow = (t + 16 * h == k);
+        al[h] = prow ? r : 1.0;
+        be[h] = prow ? 0.0 : -(R[h][k] * r);
       });
       static_for<0, Q>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         if (j <= mmax) {
-          const double b = (j == k) ? akk : rowbcast<kt>(R[kh][j]);  // K_kj before the step
-          static_for<0, H>([&](auto hh) {
-            constexpr int h = decltype(hh)::value;
-            const bool prow = (t + 16 * h == k);
-            double v;
-            if (j == k) v = prow ? -r : f[h];
-            else v = prow ? b * r : R[h][j] - f[h] * b;
-            R[h][j] = v;
-          });
+          if constexpr (j == k) {
+            static_for<0, H>([&](auto hh) {
+              constexpr int h = decltype(hh)::value;
+              R[h][j] = (t + 16 * h == k) ? -r : -be[h];
+            });
+          } else {
+            // K_kj before the step, read before any row of this column changes
+            const double b = rowbcast<kt>(R[kh][j]);
+            static_for<0, H>([&](auto hh) {
+              constexpr int h = decltype(hh)::value;
+              R[h][j] = fmaT(be[h], b, al[h] * R[h][j]);
+            });
+          }
         }
       });
     }
