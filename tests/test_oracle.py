@@ -351,6 +351,53 @@ def test_status_flags_and_isolation(oracle_lib):
     assert (rm["status"] & oracle_lib.MAXIT).all()
 
 
+def test_status_not_pd_forced(oracle_lib):
+    """NOT_PD, forced from the inputs.  A negative starting multiplier makes
+    the first Newton matrix Gh + diag(lambda / a) indefinite (its diagonal is
+    at most 1 - N), so its Cholesky factorisation breaks down before the
+    first step: the pixel keeps the start point, and the covariance of that
+    iterate is undefined.  A library entry that is not finite makes every
+    Newton matrix non-finite, which must read as the same failure, not as an
+    iteration cap or an uncertified result."""
+    S, X, s = _sample("tiny", 12)
+    N = S.shape[0]
+    r = _run(oracle_lib, S, X, s, lambda0=-1.0)
+    assert (r["status"] == oracle_lib.NOT_PD).all(), r["status"]
+    assert (r["iters"] == 0).all()
+    assert np.array_equal(r["a"], np.full((12, N), 1.0 / N))
+    assert np.isnan(r["cov"]).all()
+    Sb = S.copy()
+    Sb[2, 10] = np.inf
+    r2 = _run(oracle_lib, Sb, X, s)
+    assert (r2["status"] & oracle_lib.NOT_PD).all(), r2["status"]
+    assert not (r2["status"] & (oracle_lib.MAXIT | oracle_lib.INEXACT)).any(), r2["status"]
+
+
+def test_status_degenerate_forced(oracle_lib):
+    """DEGENERATE, forced by exact mixtures.  With y = a_true S exactly the
+    residual at the minimiser is zero, so the gradient, nu and every
+    multiplier vanish: each spectrum outside the support has a_i = 0 and
+    lambda_i = 0 (no strict complementarity).  The result is still certified
+    and exact.  The same mixtures with noise are strictly complementary."""
+    rng = np.random.default_rng(5)
+    N, L = 8, 64
+    S = (rng.integers(1, 256, (N, L)) / 256.0).astype(np.float32)
+    fracs = [(1.0,), (0.5, 0.5), (0.5, 0.25, 0.25)]
+    A = np.zeros((30, N))
+    for p in range(30):
+        f = fracs[p % len(fracs)]
+        A[p, rng.choice(N, len(f), replace=False)] = f
+    X = (A @ S.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(X.astype(np.float64), A @ S.astype(np.float64))
+    sig = np.full(30, 0.01, np.float32)
+    r = _run(oracle_lib, S, X, sig)
+    assert (r["status"] == oracle_lib.DEGENERATE).all(), r["status"]
+    assert np.abs(r["a"] - A).max() <= 1e-10
+    Xn = (X + 0.01 * rng.standard_normal(X.shape)).astype(np.float32)
+    rn = _run(oracle_lib, S, Xn, sig)
+    assert (rn["status"] == 0).mean() >= 0.9, rn["status"]
+
+
 def test_empty_input(oracle_lib):
     S, X, s = _sample("tiny", 1)
     r = _run(oracle_lib, S, X[:0], s[:0])
