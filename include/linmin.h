@@ -45,6 +45,8 @@ typedef struct linmin_lib_s *linmin_lib;
 #define LINMIN_ENOTSPD (-4)      /* noise covariance not symmetric positive definite,
                                     or the library's Gram matrix is not positive */
 #define LINMIN_EUNSUPPORTED (-5) /* option combination not built in */
+#define LINMIN_ESCRATCH (-6)     /* linmin_unmix_noalloc: the call needs more work
+                                    area than LINMIN_NOALLOC_SCRATCH_BYTES */
 
 /* precision of the interior-point iterations */
 #define LINMIN_FP64 0  /* every step in FP64 */
@@ -156,6 +158,29 @@ int linmin_unmix(linmin_lib lib, const float *cube, int64_t P, const float *sigm
 
 /* Bytes of temporary device memory linmin_unmix takes for these arguments. */
 size_t linmin_workspace_bytes(linmin_lib lib, int64_t P, const linmin_opts *opts);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * linmin_unmix with the same arguments, results and errors, except that its
+ * temporary memory is a fixed array of LINMIN_NOALLOC_SCRATCH_BYTES inside
+ * the library, one per GPU, held from the first call on that GPU until the
+ * process ends.  The call allocates and frees nothing; the caller still
+ * passes every input and output.
+ *   Limit: linmin_workspace_bytes(lib, P, opts) (with the same out_cov
+ *   presence) must not exceed LINMIN_NOALLOC_SCRATCH_BYTES, else the call
+ *   returns LINMIN_ESCRATCH and enqueues nothing; split larger cubes into
+ *   row ranges (pixels are independent).  For the FP64 path with FULL
+ *   covariance that is about 113,000 pixels at N = 36.
+ *   Concurrency: every call on one GPU uses that GPU's one array, so calls
+ *   whose work overlaps in time on the same GPU (different streams, or
+ *   different host threads) race and produce wrong results; order them on
+ *   one stream or with events.  The array keeps the last call's contents;
+ *   nothing in it needs to start at zero.
+ */
+#define LINMIN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int linmin_unmix_noalloc(linmin_lib lib, const float *cube, int64_t P, const float *sigma,
+                         double *out_coeffs, double *out_cov, const linmin_opts *opts, void *stream);
 
 /* Library shape and scale: any output pointer may be NULL.  gamma is
  * max_i G_ii of the renormalised Gram matrix.  Returns EINVAL for NULL lib. */

@@ -44,7 +44,7 @@ def _compile(src, obj, extra=()):
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = []
-    for name in ("gemm.hip", "setup.hip", "cov.hip", "detect.hip", "linmin.cpp", "ipm_dispatch.cpp"):
+    for name in ("gemm.hip", "setup.hip", "cov.hip", "detect.hip", "linmin.cpp", "ipm_dispatch.cpp", "noalloc.hip"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), ()))
     for t, nc, g in shapes():
         units.append((os.path.join(CSRC, "ipm.hip"), os.path.join(BUILD, f"ipm_{t}_{nc}_{g}.o"),

@@ -18,6 +18,7 @@
 
 #include "../../include/linmin.h"
 #include "kernels.h"
+#include "unmix.h"
 
 struct linmin_lib_s {
   int L, N, NC, ldw, dev;
@@ -177,6 +178,76 @@ int check_opts(const linmin_opts& o) {
 
 }  // namespace
 
+namespace lm {
+
+// Checks of linmin_unmix and its variants: fills *o (defaults where opts is
+// NULL) and *bytes (the work area one call needs, 0 when P == 0).
+int unmix_check(linmin_lib lib, const float* cube, int64_t P, const double* out_coeffs, const double* out_cov,
+                const linmin_opts* opts, linmin_opts* o, size_t* bytes) {
+  *bytes = 0;
+  if (!lib || P < 0) return LINMIN_EINVAL;
+  if (opts) *o = *opts;
+  else linmin_default_opts(o);
+  const int rc0 = check_opts(*o);
+  if (rc0 != LINMIN_OK) return rc0;
+  if (P == 0) return LINMIN_OK;
+  if (!cube || !out_coeffs) return LINMIN_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LINMIN_EHIP;
+  if (dev != lib->dev) return LINMIN_EINVAL;
+  *bytes = plan(lib, P, *o, out_cov != nullptr && o->cov_layout != LINMIN_COV_NONE).total;
+  return LINMIN_OK;
+}
+
+// The unmix itself (projections, interior point, covariance) on stream st
+// with the work area ws of at least unmix_check's bytes, laid out by plan().
+// Nothing here allocates; every byte of ws that a kernel reads was written
+// earlier in the same call, so ws may hold anything on entry.
+int unmix_ws(linmin_lib lib, const float* cube, int64_t P, const float* sigma, double* out_coeffs,
+             double* out_cov, const linmin_opts& o, hipStream_t st, char* ws) {
+  const bool want_cov = out_cov != nullptr && o.cov_layout != LINMIN_COV_NONE;
+  const Work w = plan(lib, P, o, want_cov);
+  auto at = [&](size_t off) -> char* { return off == (size_t)-1 ? nullptr : ws + off; };
+  double* bh = (double*)at(w.bh);
+  double* c = (double*)at(w.c);
+  uint8_t* status = o.status ? o.status : (uint8_t*)at(w.status);
+  int rc = LINMIN_OK;
+
+  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(o.stage_events);
+  auto mark = [&](int i) {
+    if (ev && hipEventRecord(ev[i], st) != hipSuccess) return LINMIN_EHIP;
+    return LINMIN_OK;
+  };
+  // projections bh = Y Wh and c = y^T C^{-1} y
+  rc = mark(0);
+  if (rc == LINMIN_OK) rc = from_launch(launch_gemm_proj_f64(cube, P, lib->L, lib->Wh, lib->ldw, lib->N, bh, c, st));
+  if (rc == LINMIN_OK && lib->Ci) rc = from_launch(launch_quadform_f64(cube, P, lib->L, lib->Ci, lib->L, c, st));
+  if (rc == LINMIN_OK && o.keep) rc = from_launch(launch_keep(lib->N, P, o.keep, c, lib->gamma, bh, st));
+  if (rc == LINMIN_OK) rc = mark(1);
+  if (rc == LINMIN_OK) {
+    IpmParams prm = make_ipm(lib, P, sigma, out_coeffs, status, o.iters, o.objective, o, w, ws, want_cov);
+    if (o.precision == LINMIN_MIXED) {
+      prm.Gh = lib->Gh32;
+      rc = from_launch(launch_ipm(prm, kStage1, true, st));
+      if (rc == LINMIN_OK) {
+        prm.Gh = lib->Gh64;
+        rc = from_launch(launch_ipm(prm, kStage2, false, st));
+      }
+    } else {
+      prm.Gh = lib->Gh64;
+      rc = from_launch(launch_ipm(prm, kFull, false, st));
+    }
+  }
+  if (rc == LINMIN_OK) rc = mark(2);
+  if (rc == LINMIN_OK && want_cov)
+    rc = from_launch(launch_cov(lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), (double*)at(w.dcorner), sigma,
+                                lib->gamma, status, o.cov_layout, out_cov, (uint8_t*)at(w.big), st));
+  if (rc == LINMIN_OK) rc = mark(3);
+  return rc;
+}
+
+}  // namespace lm
+
 extern "C" {
 
 void linmin_default_opts(linmin_opts* o) {
@@ -209,6 +280,7 @@ const char* linmin_strerror(int code) {
     case LINMIN_EHIP: return "HIP runtime or kernel launch failure";
     case LINMIN_ENOTSPD: return "matrix not symmetric positive definite";
     case LINMIN_EUNSUPPORTED: return "unsupported option combination";
+    case LINMIN_ESCRATCH: return "work area larger than the no-allocation scratch array";
     default: return "unknown error";
   }
 }
@@ -356,61 +428,16 @@ size_t linmin_workspace_bytes(linmin_lib lib, int64_t P, const linmin_opts* opts
 
 int linmin_unmix(linmin_lib lib, const float* cube, int64_t P, const float* sigma, double* out_coeffs,
                  double* out_cov, const linmin_opts* opts, void* stream) {
-  if (!lib || P < 0) return LINMIN_EINVAL;
   linmin_opts o;
-  if (opts) o = *opts;
-  else linmin_default_opts(&o);
+  size_t bytes = 0;
   {
-    const int rc0 = check_opts(o);
-    if (rc0 != LINMIN_OK) return rc0;
+    const int rc0 = lm::unmix_check(lib, cube, P, out_coeffs, out_cov, opts, &o, &bytes);
+    if (rc0 != LINMIN_OK || P == 0) return rc0;
   }
-  if (P == 0) return LINMIN_OK;
-  if (!cube || !out_coeffs) return LINMIN_EINVAL;
-  const bool want_cov = out_cov != nullptr && o.cov_layout != LINMIN_COV_NONE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return LINMIN_EHIP;
-  if (dev != lib->dev) return LINMIN_EINVAL;
-
-  const Work w = plan(lib, P, o, want_cov);
   char* ws = nullptr;
-  if (hipMallocAsync((void**)&ws, w.total, st) != hipSuccess) return LINMIN_ENOMEM;
-  auto at = [&](size_t off) -> char* { return off == (size_t)-1 ? nullptr : ws + off; };
-  double* bh = (double*)at(w.bh);
-  double* c = (double*)at(w.c);
-  uint8_t* status = o.status ? o.status : (uint8_t*)at(w.status);
-  int rc = LINMIN_OK;
-
-  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(o.stage_events);
-  auto mark = [&](int i) {
-    if (ev && hipEventRecord(ev[i], st) != hipSuccess) return LINMIN_EHIP;
-    return LINMIN_OK;
-  };
-  // projections bh = Y Wh and c = y^T C^{-1} y
-  rc = mark(0);
-  if (rc == LINMIN_OK) rc = from_launch(lm::launch_gemm_proj_f64(cube, P, lib->L, lib->Wh, lib->ldw, lib->N, bh, c, st));
-  if (rc == LINMIN_OK && lib->Ci) rc = from_launch(lm::launch_quadform_f64(cube, P, lib->L, lib->Ci, lib->L, c, st));
-  if (rc == LINMIN_OK && o.keep) rc = from_launch(lm::launch_keep(lib->N, P, o.keep, c, lib->gamma, bh, st));
-  if (rc == LINMIN_OK) rc = mark(1);
-  if (rc == LINMIN_OK) {
-    lm::IpmParams prm = make_ipm(lib, P, sigma, out_coeffs, status, o.iters, o.objective, o, w, ws, want_cov);
-    if (o.precision == LINMIN_MIXED) {
-      prm.Gh = lib->Gh32;
-      rc = from_launch(lm::launch_ipm(prm, lm::kStage1, true, st));
-      if (rc == LINMIN_OK) {
-        prm.Gh = lib->Gh64;
-        rc = from_launch(lm::launch_ipm(prm, lm::kStage2, false, st));
-      }
-    } else {
-      prm.Gh = lib->Gh64;
-      rc = from_launch(lm::launch_ipm(prm, lm::kFull, false, st));
-    }
-  }
-  if (rc == LINMIN_OK) rc = mark(2);
-  if (rc == LINMIN_OK && want_cov)
-    rc = from_launch(lm::launch_cov(lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), (double*)at(w.dcorner),
-                                    sigma, lib->gamma, status, o.cov_layout, out_cov, (uint8_t*)at(w.big), st));
-  if (rc == LINMIN_OK) rc = mark(3);
+  if (hipMallocAsync((void**)&ws, bytes, st) != hipSuccess) return LINMIN_ENOMEM;
+  int rc = lm::unmix_ws(lib, cube, P, sigma, out_coeffs, out_cov, o, st, ws);
   if (hipFreeAsync(ws, st) != hipSuccess && rc == LINMIN_OK) rc = LINMIN_EHIP;
   return rc;
 }

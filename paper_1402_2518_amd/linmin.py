@@ -15,14 +15,17 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblinmin.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EUNSUPPORTED, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 COV_NONE, COV_FULL, COV_PACKED, COV_DIAG = 0, 1, 2, 3
 STO, SLO, POS = 0, 1, 2  # sum-to-one, sum-lower-than-one, positivity only
 PX_MAXIT, PX_NONFINITE, PX_BAD_SIGMA, PX_NOT_PD, PX_DEGENERATE, PX_INEXACT = 1, 2, 4, 8, 16, 32
 N_MAX = 128
 
-EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linmin_workspace_bytes",
+NOALLOC_SCRATCH_BYTES = 64 << 20  # LINMIN_NOALLOC_SCRATCH_BYTES
+
+EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linmin_unmix_noalloc",
+           "linmin_workspace_bytes",
            "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror",
            "linmin_extra_spectra", "linmin_batch_create", "linmin_batch_run", "linmin_batch_device_bytes",
            "linmin_batch_destroy", "linmin_error_maps", "linmin_thresholds", "linmin_detect")
@@ -67,6 +70,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.linmin_create_library.restype = ctypes.c_int
         lib.linmin_unmix.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(Opts), vp]
         lib.linmin_unmix.restype = ctypes.c_int
+        lib.linmin_unmix_noalloc.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(Opts), vp]
+        lib.linmin_unmix_noalloc.restype = ctypes.c_int
         lib.linmin_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Opts)]
         lib.linmin_workspace_bytes.restype = ctypes.c_size_t
         lib.linmin_library_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -180,8 +185,13 @@ class Library:
         return int(load().linmin_workspace_bytes(self._h, int(P), ctypes.byref(o)))
 
     def unmix_into(self, cube, sigma, out_a, out_cov=None, status=None, iters=None, objective=None,
-                   precision: str = "fp64", cov: str | None = "full", stream=None, events=None, keep=None, **opts):
+                   precision: str = "fp64", cov: str | None = "full", stream=None, events=None, keep=None,
+                   noalloc: bool = False, **opts):
         """Enqueue one unmix on ``stream`` into caller-provided device tensors.
+
+        ``noalloc``: call ``linmin_unmix_noalloc`` (work areas in the
+        library's fixed device array, nothing allocated; calls on one GPU
+        must not overlap in time).
 
         ``events``: optional four ``torch.cuda.Event(enable_timing=True)``
         recorded before the projections, the solve, the covariance and after.
@@ -234,10 +244,11 @@ class Library:
                 e.record(stream)  # makes sure the underlying HIP event exists
             ev_arr = (ctypes.c_void_p * 4)(*[ctypes.c_void_p(e.cuda_event) for e in events])
             o.stage_events = ctypes.cast(ev_arr, ctypes.c_void_p)
-        rc = load().linmin_unmix(self._h, _ptr(cube), int(P), _ptr(sigma), _ptr(out_a), _ptr(out_cov),
-                                 ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        fn = load().linmin_unmix_noalloc if noalloc else load().linmin_unmix
+        rc = fn(self._h, _ptr(cube), int(P), _ptr(sigma), _ptr(out_a), _ptr(out_cov),
+                ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
         if rc != OK:
-            raise LinminError(rc, "linmin_unmix")
+            raise LinminError(rc, "linmin_unmix_noalloc" if noalloc else "linmin_unmix")
 
     def error_maps(self, cube, coeffs, cov_out=None, cov: str = "full", stream=None):
         """RMS map (P) of the fit residual y - a S in reflectance units, and

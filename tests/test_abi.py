@@ -40,6 +40,9 @@ def test_constants_match_header():
     assert int(defs["LINMIN_OK"]) == linmin.OK
     assert int(defs["LINMIN_EINVAL"]) == linmin.EINVAL
     assert int(defs["LINMIN_EUNSUPPORTED"]) == linmin.EUNSUPPORTED
+    assert int(defs["LINMIN_ESCRATCH"]) == linmin.ESCRATCH
+    m = re.search(r"#define LINMIN_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == linmin.NOALLOC_SCRATCH_BYTES
     assert int(defs["LINMIN_MIXED"]) == linmin.MIXED
     assert int(defs["LINMIN_COV_DIAG"]) == linmin.COV_DIAG
     assert int(defs["LINMIN_PX_INEXACT"]) == linmin.PX_INEXACT
