@@ -4,7 +4,9 @@ Workload: N = 36 spectra (32 synthetic minerals + 4 extra continuum spectra),
 L = 240 channels, P = 128 x 4,096 = 524,288 pixels, float32 cube resident in
 HBM, per-pixel sigma.  One step = one ``linmin_unmix`` over the whole cube:
 projections (MFMA), interior-point solve with the finishing step, and the
-full FP64 covariance.  Prints one JSON line.
+full FP64 covariance.  Prints one JSON line.  Beside it: the mixed form, the
+precision cube (N = 64, L = 438, P = 640 x 480) in both forms, the many-cube
+batch, the serving loop and the CPU oracle (all host threads, then one).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -50,10 +52,125 @@ def profiled_traffic():
 
 def ipm_flops_per_iteration(n: int) -> float:
     """Algorithmic FP64 flops of one interior-point iteration for a library of
-    n spectra: L D L^T of the bordered (n+1) Newton matrix (n^3/3 + n^2),
-    two bordered solves (4 n^2), the product with the Gram matrix (2 n^2) and
-    O(n) vector work (30 n)."""
-    return n ** 3 / 3.0 + 7.0 * n ** 2 + 30.0 * n
+    n spectra: L D L^T of the n x n Newton matrix (n^3 / 3) and the O(n^2)
+    work of two solves, the bordered elimination and the product with the
+    Gram matrix (8 n^2)."""
+    return n ** 3 / 3.0 + 8.0 * n ** 2
+
+
+IPM_KERNELS = {36: "lm::ipm_tile_kernel<9, 0, 0, false>", 64: "lm::ipm_tile_kernel<16, 0, 0, true>"}
+
+
+def workload_leg(name, args, dev, stream, steps, warmup, latency_calls, variants=0, keep_host=False):
+    """One synthetic cube unmixed whole, FP64 and mixed, full covariance:
+    throughput, stage times, single-cube latency, the interior-point
+    kernel's roofline, and a sampled check of both forms against the oracle."""
+    import torch
+    import oracle
+    from paper_1402_2518_amd import linmin, synth
+
+    w = synth.WORKLOADS[name]
+    S = synth.make_library(w)
+    t_gen = time.perf_counter()
+    X, s = synth.make_cube(w, S)
+    t_gen = time.perf_counter() - t_gen
+    Xd = torch.from_numpy(X).to(dev)
+    sd = torch.from_numpy(s).to(dev)
+    P, N = w.P, w.N
+    lib = linmin.Library(S)
+    out_a = torch.empty((P, N), dtype=torch.float64, device=dev)
+    out_cov = torch.empty((P, N, N), dtype=torch.float64, device=dev)
+    status = torch.empty(P, dtype=torch.uint8, device=dev)
+    iters = torch.empty(P, dtype=torch.int32, device=dev)
+    obj = torch.empty(P, dtype=torch.float64, device=dev)
+
+    def run(precision, steps, warmup, a_out, cov="full", npix=P):
+        X_, s_ = Xd[:npix], sd[:npix]
+        a_, st_, it_, ob_ = a_out[:npix], status[:npix], iters[:npix], obj[:npix]
+        c_ = out_cov[:npix] if cov == "full" else (out_cov.view(-1)[:npix * N].view(npix, N) if cov == "diag" else None)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                lib.unmix_into(X_, s_, a_, c_, st_, it_, ob_, precision=precision, cov=cov, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                lib.unmix_into(X_, s_, a_, c_, st_, it_, ob_, precision=precision, cov=cov, stream=stream,
+                               events=evs[k])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        stage = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                           e[0].elapsed_time(e[3])] for e in evs])  # ms
+        return wall, stage
+
+    print(f"# {name}: generated cube in {t_gen:.1f}s; P={P} N={N} L={w.L}", file=sys.stderr, flush=True)
+    res, a_keep, F_keep, st_keep = {}, {}, {}, {}
+    for prec in ("fp64", "mixed"):
+        buf = out_a if prec == "fp64" else torch.empty_like(out_a)
+        wall, st = run(prec, steps, warmup, buf)
+        it = iters.cpu().numpy()
+        stat = status.cpu().numpy()
+        a_keep[prec], F_keep[prec], st_keep[prec] = buf, obj.clone(), stat
+        res[prec] = {"value": P * steps / wall, "ms_per_step": wall / steps * 1e3,
+                     "stages_ms": {"projection": float(np.mean(st[:, 0])), "ipm": float(np.mean(st[:, 1])),
+                                   "covariance": float(np.mean(st[:, 2]))},
+                     "mean_iters": float(it.mean()),
+                     "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stat, return_counts=True))}}
+        if prec == "fp64":
+            ipm_ms = float(np.mean(st[:, 1]))
+            flops = float(it.astype(np.float64).sum()) * ipm_flops_per_iteration(N)
+            achieved = flops / (ipm_ms * 1e-3)
+            kname = IPM_KERNELS.get(N, "interior point")
+            roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64, "traffic": profiled_traffic() if N == 36 else None,
+                    "kernel": kname + " (FP64, 4x4x4 matrix-core tiles)", "kernel_ms": ipm_ms,
+                    "flops_per_launch": flops, "mean_iters": float(it.mean()),
+                    "flops_per_iteration": ipm_flops_per_iteration(N)}
+        print(f"# {name} {prec}: {wall / steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        if latency_calls > 0:
+            _, stl = run(prec, latency_calls, 1, buf)
+            res[prec]["latency_ms"] = {"p50": float(np.percentile(stl[:, 3], 50)),
+                                       "p99": float(np.percentile(stl[:, 3], 99)), "calls": int(latency_calls)}
+        else:
+            res[prec]["latency_ms"] = {"p50": float(np.percentile(st[:, 3], 50)),
+                                       "p99": float(np.percentile(st[:, 3], 99)), "calls": int(len(st))}
+    res["mixed"]["max_abs_coeff_diff_vs_fp64"] = float((a_keep["mixed"] - a_keep["fp64"]).abs().max().item())
+    res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+
+    # both forms against the FP64 oracle on a prefix of the cube
+    n_or = min(P, args.oracle_pixels)
+    r = oracle.unmix(S, X[:n_or], s[:n_or], cov=False)
+    samp = {"pixels": n_or}
+    for prec in ("fp64", "mixed"):
+        a = a_keep[prec][:n_or].cpu().numpy()
+        F = F_keep[prec][:n_or].cpu().numpy()
+        both = (st_keep[prec][:n_or] == 0) & (r["status"] == 0)
+        samp[prec] = {"max_abs_coeff_err": float(np.abs(a - r["a"]).max()),
+                      "max_rel_objective_err": float(np.abs(F[both] / r["F"][both] - 1).max()),
+                      "status_agreement": float((st_keep[prec][:n_or] == r["status"]).mean())}
+    samp["oracle_mean_iters"] = float(r["iters"].mean())
+
+    var = {}
+    if variants > 0:
+        for prec in ("fp64", "mixed"):
+            buf = a_keep[prec]
+            for cov in ("diag", "none"):
+                wv, _ = run(prec, variants, 1, buf, cov=cov)
+                var[f"{prec}_cov_{cov}"] = {"pixels_per_s": P * variants / wv, "ms_per_call": wv / variants * 1e3}
+        shard = P // 8
+        for prec in ("fp64", "mixed"):
+            wv, _ = run(prec, variants, 1, a_keep[prec], npix=shard)
+            var[f"{prec}_cov_full_P{shard}"] = {"pixels_per_s": shard * variants / wv,
+                                                "ms_per_call": wv / variants * 1e3}
+        print(f"# {name} variants: {var}", file=sys.stderr, flush=True)
+    out = {"workload": f"{name} cube: N={N} ({w.n_minerals} minerals + {w.n_extra} extras), L={w.L}, P={P}, "
+                       "fp32 reflectance, sigma~U[0.002,0.01], full covariance",
+           "fp64": res["fp64"], "mixed": res["mixed"], "roofline": roof, "oracle_sample": samp, "variants": var}
+    if keep_host:
+        out["_host"] = (S, X, s, a_keep["fp64"].cpu().numpy())
+    lib.close()
+    del out_a, out_cov, a_keep, F_keep, Xd, sd
+    return out
 
 
 def batch_leg(args, dev, stream):
@@ -117,12 +234,18 @@ def batch_leg(args, dev, stream):
             r = oracle.unmix(S_host[i], X8, s8, cov=False)
             err = max(err, float(np.abs(ref[i][0][:8].cpu().numpy() - r["a"]).max()))
         stat = torch.cat([st for _, _, st in ref]).cpu().numpy()
+        by_n = {}
+        for wk, (_, _, st) in zip(ws, ref):
+            d = by_n.setdefault(str(wk.N), {})
+            for k, v in zip(*np.unique(st.cpu().numpy(), return_counts=True)):
+                d[str(int(k))] = d.get(str(int(k)), 0) + int(v)
         out[prec] = {"pixels_per_s": P_tot / wall_b, "ms_per_run": wall_b * 1e3,
                      "stages_ms": {"projection": stages[0], "ipm": stages[1], "covariance": stages[2]},
                      "sequential_pixels_per_s": P_tot / wall_s, "sequential_ms_per_run": wall_s * 1e3,
                      "speedup_vs_sequential": wall_s / wall_b, "identical_to_single_calls": bool(same),
                      "max_abs_coeff_err_vs_oracle_sample": err,
                      "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stat, return_counts=True))},
+                     "status_counts_by_N": by_n,
                      "device_bytes": b.device_bytes()}
         print(f"# batch {prec}: {out[prec]}", file=sys.stderr, flush=True)
         b.close()
@@ -201,6 +324,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds-1core", type=float, default=4.0)
+    ap.add_argument("--oracle-pixels", type=int, default=8192,
+                    help="cube prefix checked against the oracle in each workload leg")
+    ap.add_argument("--precision-steps", type=int, default=10,
+                    help="timed whole-cube calls of the precision cube (N=64, L=438; 0 = skip)")
+    ap.add_argument("--precision-latency-calls", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200,
                     help="sequential whole-cube calls behind the p50/p99 latency")
@@ -224,24 +353,10 @@ def main():
 
     import torch
     import oracle
-    from paper_1402_2518_amd import linmin, synth
+    from paper_1402_2518_amd import synth
 
-    w = synth.WORKLOADS["orbital"]
-    S = synth.make_library(w)
-    t_gen = time.perf_counter()
-    X, s = synth.make_cube(w, S)
-    t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    sd = torch.from_numpy(s).to(dev)
-    P, N = w.P, w.N
-    lib = linmin.Library(S)
     stream = torch.cuda.Stream()
-    out_a = torch.empty((P, N), dtype=torch.float64, device=dev)
-    out_cov = torch.empty((P, N, N), dtype=torch.float64, device=dev)
-    status = torch.empty(P, dtype=torch.uint8, device=dev)
-    iters = torch.empty(P, dtype=torch.int32, device=dev)
-    obj = torch.empty(P, dtype=torch.float64, device=dev)
 
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
@@ -253,77 +368,18 @@ def main():
         print(f"# copy calibration: {nb} bytes read, {nb} bytes written", file=sys.stderr, flush=True)
         del src_t, dst_t
 
-    def run(precision, steps, warmup, a_out, cov="full", npix=P):
-        X_, s_ = Xd[:npix], sd[:npix]
-        a_, st_, it_, ob_ = a_out[:npix], status[:npix], iters[:npix], obj[:npix]
-        c_ = out_cov[:npix] if cov == "full" else (out_cov.view(-1)[:npix * N].view(npix, N) if cov == "diag" else None)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-        with torch.cuda.stream(stream):
-            for _ in range(warmup):
-                lib.unmix_into(X_, s_, a_, c_, st_, it_, ob_, precision=precision, cov=cov, stream=stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(steps):
-                lib.unmix_into(X_, s_, a_, c_, st_, it_, ob_, precision=precision, cov=cov, stream=stream,
-                               events=evs[k])
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-        stage = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
-                           e[0].elapsed_time(e[3])] for e in evs])  # ms
-        return wall, stage
-
-    print(f"# generated cube in {t_gen:.1f}s; P={P} N={N} L={w.L}", file=sys.stderr, flush=True)
-    wall64, st64 = run("fp64", args.steps, args.warmup, out_a)
-    it64 = iters.cpu().numpy()
-    stat64 = status.cpu().numpy()
-    a64 = out_a.clone()
-    print(f"# fp64: {wall64 / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
-    out_a_mix = torch.empty_like(out_a)
-    wallmx, stmx = run("mixed", args.steps, args.warmup, out_a_mix)
-    itmx = iters.cpu().numpy()
-    print(f"# mixed: {wallmx / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
-    mix_err = float((out_a_mix - a64).abs().max().item())
-
-    # single-cube latency: sequential calls, device time of each call
-    lat = {}
-    if args.latency_calls > 0:
-        for prec, buf in (("fp64", out_a), ("mixed", out_a_mix)):
-            _, stl = run(prec, args.latency_calls, 1, buf)
-            lat[prec] = {"p50": float(np.percentile(stl[:, 3], 50)), "p99": float(np.percentile(stl[:, 3], 99)),
-                         "calls": int(args.latency_calls)}
-        print(f"# latency: {lat}", file=sys.stderr, flush=True)
-    # other covariance layouts and one GPU's share of an 8-way pixel split
-    variants = {}
-    if args.variants > 0:
-        for prec, buf in (("fp64", out_a), ("mixed", out_a_mix)):
-            for cov in ("diag", "none"):
-                wv, _ = run(prec, args.variants, 1, buf, cov=cov)
-                variants[f"{prec}_cov_{cov}"] = {"pixels_per_s": P * args.variants / wv,
-                                                 "ms_per_call": wv / args.variants * 1e3}
-        shard = P // 8
-        for prec, buf in (("fp64", out_a), ("mixed", out_a_mix)):
-            wv, _ = run(prec, args.variants, 1, buf, npix=shard)
-            variants[f"{prec}_cov_full_P{shard}"] = {"pixels_per_s": shard * args.variants / wv,
-                                                     "ms_per_call": wv / args.variants * 1e3}
-        print(f"# variants: {variants}", file=sys.stderr, flush=True)
-
-    # roofline of the dominant kernel (interior-point solve)
-    ipm_ms = float(np.mean(st64[:, 1]))
-    flops = float(it64.astype(np.float64).sum()) * ipm_flops_per_iteration(N)
-    achieved = flops / (ipm_ms * 1e-3)
-    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64, "traffic": profiled_traffic(),
-            "kernel": IPM_KERNEL + " (FP64, 4x4x4 matrix-core tiles)", "kernel_ms": ipm_ms,
-            "flops_per_launch": flops, "mean_iters": float(it64.mean())}
-
+    orb = workload_leg("orbital", args, dev, stream, args.steps, args.warmup, args.latency_calls,
+                       variants=args.variants, keep_host=not args.no_cpu)
+    w = synth.WORKLOADS["orbital"]
+    P, N = w.P, w.N
     result = {
         "metric": "pixels unmixed/sec (N=36,L=240) plain FP64 vs mixed; p50/p99 cube latency",
-        "value": P * args.steps / wall64,
+        "value": orb["fp64"]["value"],
         "unit": "pixels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall64 / args.steps * 1e3,
+        "ms_per_step": orb["fp64"]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -332,24 +388,23 @@ def main():
         "config": {"workload": "orbital cube: N=36 (32 minerals + 4 extras), L=240, P=128x4096=524288, "
                                "fp32 reflectance, sigma~U[0.002,0.01], FP64 solve, full covariance",
                    "global_batch": P, "seq_len": w.L, "parallelism": "single GPU"},
-        "latency_ms": lat.get("fp64", {"p50": float(np.percentile(st64[:, 3], 50)),
-                                       "p99": float(np.percentile(st64[:, 3], 99)), "calls": int(len(st64))}),
-        "stages_ms": {"projection": float(np.mean(st64[:, 0])), "ipm": ipm_ms,
-                      "covariance": float(np.mean(st64[:, 2]))},
-        "mixed": {"value": P * args.steps / wallmx, "ms_per_step": wallmx / args.steps * 1e3,
-                  "stages_ms": {"projection": float(np.mean(stmx[:, 0])), "ipm": float(np.mean(stmx[:, 1])),
-                                "covariance": float(np.mean(stmx[:, 2]))},
-                  "latency_ms": lat.get("mixed", {"p50": float(np.percentile(stmx[:, 3], 50)),
-                                                  "p99": float(np.percentile(stmx[:, 3], 99)),
-                                                  "calls": int(len(stmx))}),
-                  "max_abs_coeff_diff_vs_fp64": mix_err, "mean_iters": float(itmx.mean())},
-        "variants": variants,
-        "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stat64, return_counts=True))},
-        "roofline": roof,
+        "latency_ms": orb["fp64"]["latency_ms"],
+        "stages_ms": orb["fp64"]["stages_ms"],
+        "mixed": orb["mixed"],
+        "variants": orb["variants"],
+        "status_counts": orb["fp64"]["status_counts"],
+        "oracle_sample": orb["oracle_sample"],
+        "roofline": orb["roofline"],
     }
+    host = orb.pop("_host", None)
+    torch.cuda.empty_cache()
+    if args.precision_steps > 0:
+        pc = workload_leg("precision", args, dev, stream, args.precision_steps, 2, args.precision_latency_calls)
+        pc.pop("_host", None)
+        result["precision_cube"] = pc
+        torch.cuda.empty_cache()
 
     if args.batch_cubes > 0:
-        del out_cov
         torch.cuda.empty_cache()
         result["batch"] = batch_leg(args, dev, stream)
 
@@ -361,10 +416,10 @@ def main():
             result["serving_light"] = serve_leg(args, dev, rate=args.serve_light_rate, seconds=20.0)
 
     if not args.no_cpu:
+        S, X, s, a64h = host
         oracle.build(force=False)
         done, cpu_time, p0, chunk = 0, 0.0, 0, 16384
         max_err = 0.0
-        a64h = a64.cpu().numpy()
         while cpu_time < args.cpu_seconds and p0 < P:
             p1 = min(P, p0 + chunk)
             t1 = time.perf_counter()
@@ -373,9 +428,22 @@ def main():
             max_err = max(max_err, float(np.abs(r["a"] - a64h[p0:p1]).max()))
             done += p1 - p0
             p0 = p1
-        result["cpu_baseline"] = {"value": done / cpu_time, "unit": "pixels/s", "cores": oracle.max_threads(),
+        cores = oracle.max_threads()
+        # the same oracle on one thread, over a smaller prefix (this leaves the
+        # oracle's thread count at one, so it runs last)
+        done1, cpu1, p0 = 0, 0.0, 0
+        while cpu1 < args.cpu_seconds_1core and p0 < P:
+            p1 = min(P, p0 + 1024)
+            t1 = time.perf_counter()
+            oracle.unmix(S, X[p0:p1], s[p0:p1], cov=True, threads=1)
+            cpu1 += time.perf_counter() - t1
+            done1 += p1 - p0
+            p0 = p1
+        result["cpu_baseline"] = {"value": done / cpu_time, "unit": "pixels/s", "cores": cores,
                                   "kind": "oracle",
-                                  "sample": f"first {done} pixels of the same cube, FP64 with full covariance"}
+                                  "sample": f"first {done} pixels of the same cube, FP64 with full covariance",
+                                  "value_1core": done1 / cpu1, "cores_1core": 1,
+                                  "sample_1core": f"first {done1} pixels of the same cube, one thread"}
         result["parity_sample"] = {"pixels": done, "max_abs_coeff_err_fp64_vs_oracle": max_err}
     print(json.dumps(result), flush=True)
 
