@@ -33,6 +33,11 @@ def tiles():
     return re.findall(r"^LM_TILE\((\d+)\)", txt, re.M)
 
 
+def rc_tiles():
+    txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
+    return re.findall(r"^LM_RC\((\d+)\)", txt, re.M)
+
+
 def _compile(src, obj, extra=()):
     cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -52,6 +57,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for t in tiles():
         units.append((os.path.join(CSRC, "ipm_tile.hip"), os.path.join(BUILD, f"ipm_tile_{t}.o"),
                       (f"-DLM_TILE_T={t}",)))
+    for t in rc_tiles():
+        units.append((os.path.join(CSRC, "ipm_rc.hip"), os.path.join(BUILD, f"ipm_rc_{t}.o"),
+                      (f"-DLM_RC_T={t}",)))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_compile, s, o, e) for s, o, e in units]

@@ -29,20 +29,9 @@
 // to four right-hand sides ride along (the solve carries u = H^{-1} 1 next to
 // the Newton right-hand side).  Elementwise work uses a compact layout: lane
 // (x, z) holds element 16m + 4z + x of slot m.
-#include "common.h"
-#include "kernels.h"
+#include "ipm_body.h"
 
 namespace lm {
-
-__device__ __forceinline__ double mfma4(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-
-// quad broadcast: lane (x, z) <- lane (x, R) of the same block
-template <int R>
-__device__ __forceinline__ double qb(double v) {
-  return dpp<qp(R, R, R, R)>(v);
-}
 
 // Reductions over the 16 lanes of a block (same bits on every lane): a quad
 // butterfly with DPP, then the row pair (x ^ 1) and the half-wave pair
@@ -72,22 +61,11 @@ __device__ __forceinline__ int bor_i(int v) {
   return bred(v, [](int a, int b) { return a | b; });
 }
 
-// Reciprocal to about single precision squared (one Newton step), for
-// step-to-boundary ratios, which only need a few digits.
-__device__ __forceinline__ double rcp1(double x) {
-  const double y = __builtin_amdgcn_rcp(x);
-  return y * fmaT(-x, y, 2.0);
-}
-
-template <typename T>
-__device__ __forceinline__ bool fin(T v) {
-  return isfin(v);
-}
-
-template <int T>
+template <int T, bool ST>
 struct Tile {
   static constexpr int NP = 4 * T;
   static constexpr int C = (T + 3) / 4;  // compact slots
+  static constexpr int NX = T;           // solve registers: one per tile row
   static constexpr int NT = T * (T + 1) / 2;
   static constexpr int id(int I, int J) { return I * (I + 1) / 2 + J; }
 
@@ -99,6 +77,19 @@ struct Tile {
   // and 1/d on it (zero above), H[id(I, K)] = -L_IK (I > K).
   double H[NT];
   bool notpd;
+  int nvalid;               // library size n
+
+  // compact layout: lane (x, z) holds element 16m + 4z + x of slot m
+  __device__ __forceinline__ int el(int m) const { return 16 * m + 4 * z + x; }
+  __device__ __forceinline__ bool xvalid(int I) const { return 4 * I + x < nvalid; }
+  __device__ __forceinline__ int rhs() const { return z; }
+  __device__ __forceinline__ bool writer() const { return x == 0 && z == 0; }
+
+  static __device__ __forceinline__ double sum(double v) { return bsum(v); }
+  static __device__ __forceinline__ double vmin(double v) { return bmin(v); }
+  static __device__ __forceinline__ double vmax(double v) { return bmax(v); }
+  static __device__ __forceinline__ int imin(int v) { return bmin_i(v); }
+  static __device__ __forceinline__ int ior(int v) { return bor_i(v); }
 
   // compact -> x layout (every right-hand side slot gets the same vector)
   __device__ __forceinline__ void to_x(const double (&v)[C], double (&xl)[T]) const {
@@ -155,45 +146,15 @@ struct Tile {
 
   // The symmetric 4x4 tile M held in stored form (lane (x, z) holds
   // M[z][x]) as L diag(d) L^T with unit lower L: the block's 16 lanes
-  // exchange the tile through LDS and factor it redundantly.  Each lane
-  // returns entry (z, x) of L^{-1} (1 on the diagonal, 0 above it) in li and
-  // 1 / d_x in rx.
+  // exchange the tile through LDS and factor it redundantly (ldl4_lds).
   __device__ __forceinline__ void ldl4(double h, bool& bad, double& li, double& rx) const {
     xch[z * 4 + x] = h;
     lds_sync();
-    const double m00 = xch[0], m10 = xch[4], m11 = xch[5], m20 = xch[8], m21 = xch[9];
-    const double m22 = xch[10], m30 = xch[12], m31 = xch[13], m32 = xch[14], m33 = xch[15];
-    const double d0 = m00;
-    const double r0 = rcpT(d0);
-    const double l10 = m10 * r0, l20 = m20 * r0, l30 = m30 * r0;
-    const double d1 = fmaT(-l10, m10, m11);
-    const double r1 = rcpT(d1);
-    const double t21 = fmaT(-l20, m10, m21), t31 = fmaT(-l30, m10, m31);
-    const double l21 = t21 * r1, l31 = t31 * r1;
-    const double d2 = fmaT(-l21, t21, fmaT(-l20, m20, m22));
-    const double r2 = rcpT(d2);
-    const double t32 = fmaT(-l31, t21, fmaT(-l30, m20, m32));
-    const double l32 = t32 * r2;
-    const double d3 = fmaT(-l32, t32, fmaT(-l31, t31, fmaT(-l30, m30, m33)));
-    const double r3 = rcpT(d3);
-    // pivots positive and finite; for a sum, s - s == 0 is a safe finiteness
-    // test (no product to contract with) and keeps the factor's register
-    // footprint lower than a class test here
-    const double dmin = fmin(fmin(d0, d1), fmin(d2, d3));
-    const double ds = d0 + d1 + d2 + d3;
-    bad |= !(dmin > 0.0) || !(ds == ds && ds - ds == 0.0);
-    // column x of L^{-1}: L v = e_x
-    const double e0 = x == 0 ? 1.0 : 0.0, e1 = x == 1 ? 1.0 : 0.0;
-    const double e2 = x == 2 ? 1.0 : 0.0, e3 = x == 3 ? 1.0 : 0.0;
-    const double v1 = fmaT(-l10, e0, e1);
-    const double v2 = fmaT(-l21, v1, fmaT(-l20, e0, e2));
-    const double v3 = fmaT(-l32, v2, fmaT(-l31, v1, fmaT(-l30, e0, e3)));
-    li = z == 0 ? e0 : (z == 1 ? v1 : (z == 2 ? v2 : v3));
-    rx = x == 0 ? r0 : (x == 1 ? r1 : (x == 2 ? r2 : r3));
+    ldl4_lds(xch, x, z, bad, li, rx);
   }
 
   // tiled right-looking L D L^T of H
-  __device__ __forceinline__ void factor() {
+  __device__ __forceinline__ void factor_st() {
     bool bad = false;
     static_for<0, T>([&](auto kk) {
       constexpr int K = decltype(kk)::value;
@@ -219,7 +180,7 @@ struct Tile {
   }
 
   // solve L D L^T X = R in place (x layout, one right-hand side per z)
-  __device__ __forceinline__ void solve(double (&xr)[T]) const {
+  __device__ __forceinline__ void solve_st(double (&xr)[T]) const {
     // L y = r: the unit lower diagonal block, then the blocks below it
     static_for<0, T>([&](auto jj) {
       constexpr int J = decltype(jj)::value;
@@ -341,16 +302,22 @@ struct Tile {
       });
     });
   }
+
+  __device__ __forceinline__ void factor() {
+    if constexpr (ST) factor_st(); else factor_inv();
+  }
+  __device__ __forceinline__ void solve(double (&xr)[T]) const {
+    if constexpr (ST) solve_st(xr); else solve_inv(xr);
+  }
 };
 
 // One workgroup's 16 pixels: workgroup wg of the cube described by prm.
-// ST: the stable factorisation (factor/solve) rather than explicit inverses
-// of the diagonal blocks (factor_inv/solve_inv).
+// ST: the stable factorisation (factor_st/solve_st) rather than explicit
+// inverses of the diagonal blocks (factor_inv/solve_inv).
 template <int T, int MODE, int CONS, bool ST>
 __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) {
-  using TL = Tile<T>;
+  using TL = Tile<T, ST>;
   constexpr int NP = TL::NP;
-  constexpr int C = TL::C;
   __shared__ double sG[NP * NP];
   __shared__ double sx[16 * 18];
   const double* Gsrc = static_cast<const double*>(prm.Gh);
@@ -361,8 +328,6 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
   const int blk = (lane >> 2) & 3, x = lane >> 4, z = lane & 3;
   const int pib = wave * 4 + blk;
   const int64_t p = wg * 16 + pib;
-  const bool inrange = p < prm.P;
-  const int n = prm.n;
 
   TL tl;
   tl.x = x;
@@ -370,393 +335,8 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
   tl.blk = blk;
   tl.sG = sG;
   tl.xch = sx + pib * 18;
-
-  bool vm[C];
-  static_for<0, C>([&](auto mm) { vm[mm] = (16 * mm + 4 * z + x) < n; });
-  auto el = [&](int m) { return 16 * m + 4 * z + x; };
-  // x-layout validity of element 4I + x
-  auto vx = [&](int I) { return 4 * I + x < n; };
-
-  uint32_t flags = 0;
-  double bh[C];
-  bool nonfin = false;
-  static_for<0, C>([&](auto mm) {
-    constexpr int m = decltype(mm)::value;
-    const double v = (inrange && vm[m]) ? prm.bh[p * n + el(m)] : 0.0;
-    if (!fin(v)) nonfin = true;
-    bh[m] = v;
-  });
-  if (inrange && prm.c && !fin(prm.c[p])) nonfin = true;
-  nonfin = bor_i((int)nonfin) != 0;
-  if (nonfin) {
-    flags |= kPxNonfinite;
-    static_for<0, C>([&](auto mm) { bh[mm] = 0.0; });
-  }
-  double bhmax = 0.0;
-  static_for<0, C>([&](auto mm) { bhmax = fmax(bhmax, fabs(bh[mm])); });
-  bhmax = bmax(bhmax);
-
-  // constraint besides a >= 0: sum-to-one, sum-lower-than-one (slack s of
-  // 1^T a <= 1 with multiplier nu: one more complementarity pair), or
-  // positivity only (no sum row, nu = 0)
-  constexpr bool slo = CONS == kSlo, pos = CONS == kPos;
-  const double inv_np = 1.0 / (n + (slo ? 1 : 0));  // complementarity pairs
-  double a[C], lam[C], nu = slo ? prm.lambda0 : 0.0, s = slo ? inv_np : 0.0;
-  int it = 0;
-  bool start = inrange && !nonfin;
-  if constexpr (MODE == kStage2) {
-    if (inrange) {
-      const uint8_t f = prm.st_flag[p];
-      flags |= f & 0x7fu;
-      start = start && (f & 0x80u);
-      it = prm.st_it[p];
-      nu = prm.st_nu[p];
-      s = slo ? prm.st_s[p] : 0.0;
-    }
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      const bool ok = inrange && vm[m];
-      a[m] = ok ? prm.st_a[p * n + el(m)] : 0.0;
-      lam[m] = ok ? prm.st_lam[p * n + el(m)] : 0.0;
-    });
-  } else {
-    static_for<0, C>([&](auto mm) {
-      a[mm] = vm[mm] ? inv_np : 0.0;
-      lam[mm] = vm[mm] ? prm.lambda0 : 0.0;
-    });
-  }
-  const double tol_mu = prm.tol_mu, tol_d = prm.tol_d, tol_p = prm.tol_p, eta = prm.eta, tau = prm.tau;
-  const double inv_n = 1.0 / n;
-  constexpr double BIG = 1e30;
-
-  enum { kIpm = 0, kPol = 1, kDone = 2 };
-  int phase = start ? kIpm : kDone;
-  bool converged = false, certified = false, cand = false;
-  bool sfree = pos;  // finishing step: the sum row is absent (slack free or no sum constraint)
-  uint32_t freem = 0;  // bit m: compact slot m is free
-  int kp = 0;
-  double pa[C], pnu = 0.0;
-
-  double g[C], rd[C], D[C], dx[C], u[C], dla[C];
-  double rp = 0.0, mu = 0.0;
-  double xl[T];
-  // gradient of the quadratic at the starting point
-  tl.to_x(a, xl);
-  tl.gmul(xl, g);
-  for (;;) {
-    // Gh is re-read from LDS each step rather than held in registers across
-    // iterations (it would not fit next to the factor).
-    asm volatile("" ::: "memory");
-    // ---- phase decisions ---------------------------------------------------
-    // g = Gh a is carried from step to step (see the update below).  Where
-    // dependent spectra make the Newton matrix nearly singular, the carried
-    // g drifts from Gh a, so a pixel whose residuals pass the stopping tests
-    // confirms them with an explicit product before it stops; the finishing
-    // step's candidate gets its own product as well.
-    auto residuals = [&](double& rdm) {
-      double sa = 0.0, sal = 0.0;
-      rdm = 0.0;
-      static_for<0, C>([&](auto mm) {
-        constexpr int m = decltype(mm)::value;
-        rd[m] = vm[m] ? (g[m] - bh[m] - lam[m] + nu) : 0.0;
-        sa += a[m];
-        sal = fmaT(a[m], lam[m], sal);
-        rdm = fmax(rdm, fabs(rd[m]));
-      });
-      rp = pos ? 0.0 : bsum(sa) + s - 1.0;
-      mu = (bsum(sal) + s * nu) * inv_np;
-      rdm = bmax(rdm);
-    };
-    auto stops = [&](double rdm) {
-      if constexpr (MODE == kStage1)
-        return mu <= fmax(tol_mu, prm.mu_switch);
-      else
-        return mu <= tol_mu && rdm <= tol_d * (1.0 + bhmax) && fabs(rp) <= tol_p;
-    };
-    double rdm = 0.0;
-    bool conv = false;
-    if (phase == kIpm) {
-      residuals(rdm);
-      conv = stops(rdm);
-    }
-    const bool confirm = MODE != kStage1 && phase == kIpm && conv;
-    double gp[C];
-    if (__builtin_amdgcn_ballot_w64(confirm || (phase == kPol && cand)) != 0) {
-      double v[C];
-      static_for<0, C>([&](auto mm) { v[mm] = confirm ? a[mm] : pa[mm]; });
-      tl.to_x(v, xl);
-      tl.gmul(xl, gp);
-    }
-    if (confirm) {
-      static_for<0, C>([&](auto mm) { g[mm] = gp[mm]; });
-      residuals(rdm);
-      conv = stops(rdm);
-    }
-    if (phase == kIpm) {
-      if (conv) {
-        converged = true;
-        phase = kPol;
-        cand = false;
-        static_for<0, C>([&](auto mm) {
-          if (vm[mm] && a[mm] > lam[mm]) freem |= 1u << mm;
-        });
-        sfree = pos || (slo && s > nu);
-      } else if (it >= prm.maxit) {
-        flags |= kPxMaxit;
-        phase = kDone;
-      }
-    } else if (phase == kPol && cand) {
-      double wa = INFINITY, wl = INFINITY, pl[C];
-      static_for<0, C>([&](auto mm) {
-        constexpr int m = decltype(mm)::value;
-        const bool fr = (freem >> m) & 1u;
-        pl[m] = (vm[m] && !fr) ? gp[m] - bh[m] + pnu : 0.0;
-        if (vm[m] && fr) wa = fmin(wa, pa[m]);
-        if (vm[m] && !fr) wl = fmin(wl, pl[m]);
-      });
-      wa = bmin(wa);
-      wl = bmin(wl);
-      // sum-lower-than-one: the slack is one more index (free: its value
-      // 1 - 1^T a must be >= 0; at its bound: the multiplier nu must be)
-      double spa = 0.0;
-      static_for<0, C>([&](auto mm) { spa += pa[mm]; });
-      const double sv = 1.0 - bsum(spa);
-      const bool slA = slo && sfree && sv < fmin(wa, -tau);
-      const bool slL = slo && !sfree && pnu < fmin(wl, -tau);
-      if (slA) wa = sv;
-      if (slL) wl = pnu;
-      if (wa >= -tau && wl >= -tau) {
-        certified = true;
-        phase = kDone;
-        static_for<0, C>([&](auto mm) {
-          a[mm] = pa[mm];
-          lam[mm] = pl[mm];
-        });
-        nu = pnu;
-        s = (slo && sfree) ? sv : 0.0;
-      } else if (kp >= prm.max_polish) {
-        phase = kDone;
-      } else if ((wa < -tau && wa <= wl) ? slA : slL) {
-        sfree = !sfree;
-        ++kp;
-        cand = false;
-      } else {
-        const bool flipA = (wa < -tau) && (wa <= wl);
-        const double target = flipA ? wa : wl;
-        int idx = 1 << 30;
-        static_for<0, C>([&](auto mm) {
-          constexpr int m = decltype(mm)::value;
-          const bool fr = (freem >> m) & 1u;
-          const bool c = flipA ? (vm[m] && fr && pa[m] == target) : (vm[m] && !fr && pl[m] == target);
-          if (c) idx = min(idx, el(m));
-        });
-        idx = bmin_i(idx);
-        static_for<0, C>([&](auto mm) {
-          if (el(mm) == idx) freem ^= 1u << mm;
-        });
-        ++kp;
-        cand = false;
-      }
-    }
-    if (__builtin_amdgcn_ballot_w64(phase != kDone) == 0) break;
-
-    // ---- Newton (or finishing-step) matrix and its factorisation ----------
-    double ia[C];  // 1 / a
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      ia[m] = rcpT(a[m]);
-      const double dp = ((freem >> m) & 1u) ? 0.0 : BIG;
-      const double di = (phase == kPol) ? dp : ((phase == kIpm) ? lam[m] * ia[m] : 1.0);
-      D[m] = vm[m] ? di : 0.0;
-    });
-    tl.to_x(D, xl);
-    tl.form(xl);
-    if constexpr (ST) tl.factor(); else tl.factor_inv();
-    if (phase != kDone && tl.notpd) {
-      if (phase == kIpm) flags |= kPxNotPd;
-      phase = kDone;
-    }
-
-    // ---- first solve: [rhs, 1] (predictor / finishing), u = H^{-1} 1 ------
-    {
-      double rc[C];
-      static_for<0, C>([&](auto mm) {
-        rc[mm] = (phase == kPol) ? bh[mm] : (vm[mm] ? -rd[mm] - lam[mm] : 0.0);
-      });
-      tl.to_x(rc, xl);
-      static_for<0, T>([&](auto ii) {
-        constexpr int I = decltype(ii)::value;
-        const double one = vx(I) ? 1.0 : 0.0;
-        xl[I] = (z == 1) ? one : xl[I];
-      });
-    }
-    if constexpr (ST) tl.solve(xl); else tl.solve_inv(xl);
-    tl.template from_x<0>(xl, dx);
-    tl.template from_x<1>(xl, u);
-    double su = 0.0, sw = 0.0;
-    static_for<0, C>([&](auto mm) {
-      su += u[mm];
-      sw += dx[mm];
-    });
-    su = bsum(su);
-    sw = bsum(sw);
-    const double isu = rcpT(su);
-    if (phase == kPol) {
-      // equality-constrained problem on the free set: a = w - nu u, 1^T a = 1
-      pnu = sfree ? 0.0 : (sw - 1.0) * isu;
-      static_for<0, C>([&](auto mm) {
-        pa[mm] = (vm[mm] && ((freem >> mm) & 1u)) ? fmaT(-pnu, u[mm], dx[mm]) : 0.0;
-      });
-      cand = fin(pnu);
-      if (!cand) phase = kDone;
-    }
-    const bool two = __builtin_amdgcn_ballot_w64(phase == kIpm) != 0;
-    if (!two) continue;
-
-    // ---- predictor step and centring --------------------------------------
-    // sum row: dnu = (1^T w + r_p - rcs/nu) / (1^T u + s/nu) with the slack
-    // pair (rcs = s nu in the predictor), (1^T w + r_p) / 1^T u without it;
-    // none for positivity only; ds = (-rcs - s dnu) / nu
-    const double son = slo ? s / nu : 0.0;
-    const double dnu_aff = pos ? 0.0 : (slo ? (sw + rp - s) / (su + son) : (sw + rp) * isu);
-    const double ds_aff = slo ? -s - son * dnu_aff : 0.0;
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      dx[m] = vm[m] ? fmaT(-dnu_aff, u[m], dx[m]) : 0.0;
-      dla[m] = vm[m] ? -lam[m] - D[m] * dx[m] : 0.0;
-    });
-    double st_aff = INFINITY;
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      const double q1 = -a[m] * rcp1(dx[m]), q2 = -lam[m] * rcp1(dla[m]);
-      st_aff = (vm[m] && dx[m] < 0.0) ? fmin(st_aff, q1) : st_aff;
-      st_aff = (vm[m] && dla[m] < 0.0) ? fmin(st_aff, q2) : st_aff;
-    });
-    st_aff = fmin(bmin(st_aff), 1.0);
-    if (slo) {
-      if (ds_aff < 0.0) st_aff = fmin(st_aff, -s / ds_aff);
-      if (dnu_aff < 0.0) st_aff = fmin(st_aff, -nu / dnu_aff);
-    }
-    double smu = 0.0;
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      if (vm[m]) smu = fmaT(a[m] + st_aff * dx[m], lam[m] + st_aff * dla[m], smu);
-    });
-    const double smu_s = slo ? (s + st_aff * ds_aff) * (nu + st_aff * dnu_aff) : 0.0;
-    const double ratio = (bsum(smu) + smu_s) * inv_np * rcpT(mu);
-    const double sig = ratio * ratio * ratio;
-
-    // ---- corrector (second-order term dropped after a short affine step) ---
-    const double soc = st_aff >= 0.1 ? 1.0 : 0.0;
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      const double rcv = fmaT(soc * dx[m], dla[m], a[m] * lam[m]) - sig * mu;
-      dla[m] = vm[m] ? rcv * ia[m] : 0.0;  // rc / a
-      dx[m] = vm[m] ? -rd[m] - dla[m] : 0.0;
-    });
-    tl.to_x(dx, xl);
-    if constexpr (ST) tl.solve(xl); else tl.solve_inv(xl);
-    tl.template from_x<0>(xl, dx);
-    double sw2 = 0.0;
-    static_for<0, C>([&](auto mm) { sw2 += dx[mm]; });
-    sw2 = bsum(sw2);
-    const double rcs = slo ? fmaT(soc * ds_aff, dnu_aff, s * nu) - sig * mu : 0.0;
-    const double dnu = pos ? 0.0 : (slo ? (sw2 + rp - rcs / nu) / (su + son) : (sw2 + rp) * isu);
-    const double ds = slo ? (-rcs - s * dnu) / nu : 0.0;
-    double dl[C];
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      dx[m] = vm[m] ? fmaT(-dnu, u[m], dx[m]) : 0.0;
-      dl[m] = vm[m] ? -dla[m] - D[m] * dx[m] : 0.0;
-    });
-    double step = INFINITY;
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      const double q1 = -a[m] * rcp1(dx[m]), q2 = -lam[m] * rcp1(dl[m]);
-      step = (vm[m] && dx[m] < 0.0) ? fmin(step, q1) : step;
-      step = (vm[m] && dl[m] < 0.0) ? fmin(step, q2) : step;
-    });
-    step = bmin(step);
-    if (slo) {
-      if (ds < 0.0) step = fmin(step, -s / ds);
-      if (dnu < 0.0) step = fmin(step, -nu / dnu);
-    }
-    const double alpha = fmin(1.0, eta * step);
-    if (phase == kIpm && fin(alpha)) {
-      // the Newton equations give Gh da = -r_d + dlambda - dnu 1 exactly, so
-      // the gradient follows the step without another product with Gh
-      static_for<0, C>([&](auto mm) {
-        constexpr int m = decltype(mm)::value;
-        const double rdm = g[m] - bh[m] - lam[m] + nu;  // r_d before the step
-        g[m] = vm[m] ? fmaT(alpha, dl[m] - rdm - dnu, g[m]) : 0.0;
-        a[m] = fmaT(alpha, dx[m], a[m]);
-        lam[m] = fmaT(alpha, dl[m], lam[m]);
-      });
-      nu = fmaT(alpha, dnu, nu);
-      s = fmaT(alpha, ds, s);
-    }
-    if (phase == kIpm) ++it;
-  }
-
-  if (converged && !certified && inrange && !nonfin) flags |= kPxInexact;
-  if (certified) {
-    bool deg = false;
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      if (vm[m]) deg |= ((freem >> m) & 1u) ? (a[m] < prm.deg_tol) : (lam[m] < prm.deg_tol);
-    });
-    if (slo) deg |= sfree ? (s < prm.deg_tol) : (nu < prm.deg_tol);
-    if (bor_i((int)deg)) flags |= kPxDegenerate;
-  }
-  double sgm = 1.0;
-  if (inrange && prm.sigma) sgm = (double)prm.sigma[p];
-  if (!(sgm > 0.0) || !fin(sgm)) flags |= kPxBadSigma;
-  const double qnan = __builtin_nan("");
-  if (inrange) {
-    static_for<0, C>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      if (vm[m]) {
-        const int64_t o = p * n + el(m);
-        prm.out_a[o] = nonfin ? qnan : a[m];
-        if (prm.dcov) {
-          double dv;
-          if (nonfin) dv = qnan;
-          else if (certified) dv = ((freem >> m) & 1u) ? 0.0 : (double)INFINITY;
-          else dv = lam[m] / a[m];
-          prm.dcov[o] = dv;
-        }
-      }
-    });
-    if (prm.dcorner && x == 0 && z == 0) {
-      // corner of the bordered matrix of the covariance: 0 on a binding sum
-      // row, -s/nu for the slack pair of an uncertified iterate, -inf when
-      // there is no sum row
-      double cr;
-      if (certified) cr = sfree ? -(double)INFINITY : 0.0;
-      else cr = pos ? -(double)INFINITY : (slo ? -s / nu : 0.0);
-      prm.dcorner[p] = cr;
-    }
-  }
-  if (prm.objective) {
-    tl.to_x(a, xl);
-    tl.gmul(xl, g);
-    double ba = 0.0, aga = 0.0;
-    static_for<0, C>([&](auto mm) {
-      ba = fmaT(bh[mm], a[mm], ba);
-      aga = fmaT(a[mm], g[mm], aga);
-    });
-    ba = bsum(ba);
-    aga = bsum(aga);
-    if (inrange && x == 0 && z == 0) {
-      double F = (prm.c[p] - 2.0 * prm.gamma * ba + prm.gamma * aga) / (sgm * sgm);
-      if (nonfin || (flags & kPxBadSigma)) F = qnan;
-      prm.objective[p] = F;
-    }
-  }
-  if (inrange && x == 0 && z == 0) {
-    if (prm.status) prm.status[p] = (uint8_t)flags;
-    if (prm.iters) prm.iters[p] = it;
-  }
+  tl.nvalid = prm.n;
+  ipm_pixel<TL, MODE, CONS>(prm, p, p < prm.P, tl);
 }
 
 // waves per SIMD the register budget is sized for: two up to T = 9; beyond,
