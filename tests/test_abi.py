@@ -4,6 +4,7 @@ constants.  No GPU call is made."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -51,9 +52,25 @@ def test_constants_match_header():
         (linmin.STO, linmin.SLO, linmin.POS)
 
 
-def test_opts_struct_layout():
-    # field order and size of linmin_opts as declared in the header
-    assert ctypes.sizeof(linmin.Opts) == 5 * 4 + 4 + 8 * 8 + 5 * 8  # five ints, padding, doubles, pointers
+def test_opts_struct_layout(tmp_path):
+    # field offsets and size of linmin_opts and linmin_job as the C compiler
+    # lays them out from the header, against the ctypes mirrors
+    include = os.path.join(ROOT, "include")
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in linmin.Opts._fields_]
+    jfields = [f for f, _ in linmin.Job._fields_]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "linmin.h"', "int main(void) {",
+             '  printf("%zu\\n", sizeof(linmin_opts));', '  printf("%zu\\n", sizeof(linmin_job));']
+    lines += [f'  printf("%zu\\n", offsetof(linmin_opts, {f}));' for f in fields]
+    lines += [f'  printf("%zu\\n", offsetof(linmin_job, {f}));' for f in jfields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", include, str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(linmin.Opts) and vals[1] == ctypes.sizeof(linmin.Job)
+    assert vals[2:2 + len(fields)] == [getattr(linmin.Opts, f).offset for f in fields]
+    assert vals[2 + len(fields):] == [getattr(linmin.Job, f).offset for f in jfields]
 
 
 def test_strerror_and_defaults_without_gpu():
@@ -61,6 +78,7 @@ def test_strerror_and_defaults_without_gpu():
     assert lib.linmin_strerror(-4).decode().startswith("matrix not")
     o = linmin.default_opts()
     assert o.maxit == 200 and o.tol_mu == 1e-13 and o.precision == linmin.FP64
+    assert o.mu_switch == 1e-7
     assert o.constraint == linmin.STO
     h = ctypes.c_void_p()
     # argument errors are reported before any device work
