@@ -2,12 +2,16 @@
 
 Libraries stay resident on the device with their Gram matrices (one
 :class:`linmin.Library` each).  A request names a library and a device cube.
-Requests wait in arrival order; the head of the queue is admitted as soon as
-an execution slot is free and its HBM footprint (outputs and the call's
-workspace) fits in the budget next to the requests already running.  An
-admitted request is one ``linmin_unmix`` call on one of a few HIP streams, so
-requests of different libraries and sizes run on the device at the same time
-and new ones start while earlier ones are still running.  Every pixel is
+Requests wait in arrival order.  A waiting request is admitted as soon as an
+execution slot is free and its HBM footprint (outputs and the call's
+workspace) fits in the budget next to the requests already running; a request
+that does not fit does not block smaller ones behind it, unless it has waited
+longer than a bound, after which nothing passes it until it has started (so
+no request starves).  An admitted request is one ``linmin_unmix`` call on one
+of a few HIP streams, ordered after the work that was queued on the caller's
+stream when it was admitted (where its cube was produced), so requests of
+different libraries and sizes run on the device at the same time and new ones
+start while earlier ones are still running.  Every pixel is
 solved independently, so a request's result does not depend on what else was
 running.
 
@@ -61,11 +65,25 @@ def admissible(head_bytes: int, used_bytes: int, budget: int, running: int, slot
     return used_bytes + head_bytes <= budget
 
 
+def pick(waiting, used_bytes: int, budget: int, running: int, slots: int, now: float, max_pass_s: float):
+    """Index in ``waiting`` (arrival order) of the next request to admit, or
+    None.  The oldest request that fits goes first; a request that does not
+    fit is passed over by later ones only while it has waited less than
+    ``max_pass_s`` seconds."""
+    for i, r in enumerate(waiting):
+        if admissible(r.footprint, used_bytes, budget, running, slots):
+            return i
+        if running >= slots or now - r.arrival >= max_pass_s:
+            return None
+    return None
+
+
 class Server:
     def __init__(self, libraries: dict, streams: int = 4, slots: int = 8, hbm_budget: int = 64 << 30,
-                 precision: str = "fp64", cov: str | None = "full"):
+                 precision: str = "fp64", cov: str | None = "full", max_pass_s: float = 0.25):
         import torch
         self.libs = libraries
+        self.max_pass_s = float(max_pass_s)
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.slots = slots
         self.budget = int(hbm_budget)
@@ -78,6 +96,13 @@ class Server:
         lib = self.libs[r.lib]
         P, n = r.cube.shape[0], lib.N
         st = self.streams[k % len(self.streams)]
+        # the cube (and sigma) may still be in production on the caller's
+        # stream: order this request after it, and tell the caching allocator
+        # that the side stream uses them
+        st.wait_stream(torch.cuda.current_stream(r.cube.device))
+        r.cube.record_stream(st)
+        if r.sigma is not None:
+            r.sigma.record_stream(st)
         with torch.cuda.stream(st):
             dev = r.cube.device
             shp = {None: None, "none": None, "full": (P, n, n), "packed": (P, n * (n + 1) // 2),
@@ -120,8 +145,12 @@ class Server:
                         r.out = None
                     done.append(r)
                     busy = True
-            while waiting and admissible(waiting[0].footprint, used, self.budget, len(running), self.slots):
-                r = waiting.popleft()
+            while waiting:
+                i = pick(waiting, used, self.budget, len(running), self.slots, now, self.max_pass_s)
+                if i is None:
+                    break
+                r = waiting[i]
+                del waiting[i]
                 r.t_start = time.perf_counter() - t0
                 r.out, ev = self._launch(r, k)
                 k += 1

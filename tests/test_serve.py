@@ -23,3 +23,23 @@ def test_poisson_arrivals():
     assert abs(len(t) / 200.0 - 50.0) < 2.0  # rate
     gaps = np.diff(t)
     assert abs(gaps.mean() - 0.02) < 0.001 and abs(gaps.std() / gaps.mean() - 1) < 0.05  # exponential gaps
+
+
+def test_pick_passes_a_blocked_head_for_a_bounded_time():
+    R = serve.Request
+    big = R(0, "a", None, None, arrival=0.0)
+    small = R(1, "a", None, None, arrival=0.1)
+    big.footprint, small.footprint = 80, 10
+    w = [big, small]
+    # the head does not fit next to 50 running bytes; the smaller one does
+    assert serve.pick(w, 50, 100, 1, 4, now=0.2, max_pass_s=0.5) == 1
+    # the head has waited past the bound: nothing passes it
+    assert serve.pick(w, 50, 100, 1, 4, now=0.6, max_pass_s=0.5) is None
+    # the head fits: it goes first
+    assert serve.pick(w, 10, 100, 1, 4, now=0.2, max_pass_s=0.5) == 0
+    # no free slot
+    assert serve.pick(w, 0, 100, 4, 4, now=0.2, max_pass_s=0.5) is None
+    # nothing running: the head is admitted whatever its size
+    big.footprint = 500
+    assert serve.pick(w, 0, 100, 0, 4, now=0.2, max_pass_s=0.5) == 0
+    assert serve.pick([], 0, 100, 0, 4, now=0.0, max_pass_s=0.5) is None
