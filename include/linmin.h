@@ -98,7 +98,9 @@ typedef struct {
     double lambda0;     /* starting multipliers (0.1) */
     double tau;         /* KKT sign tolerance of the finishing step (1e-11) */
     double deg_tol;     /* strict-complementarity threshold (1e-9) */
-    double mu_switch;   /* MIXED: FP32 -> FP64 hand-over point (1e-7) */
+    double mu_switch;   /* MIXED: FP32 -> FP64 hand-over point (1e-8); the
+                           FP32 stage also hands over after 60 steps or a
+                           step below 1e-3 of the way to the boundary */
     uint8_t *status;    /* device, P entries or NULL: LINMIN_PX_* bits */
     int32_t *iters;     /* device, P entries or NULL: interior-point iterations */
     double *objective;  /* device, P entries or NULL: renormalised criterion
@@ -308,6 +310,38 @@ int linmin_thresholds(int N, int64_t P, const double *coeffs, const uint8_t *pre
  */
 int linmin_detect(int N, int64_t P, const double *coeffs, const double *sigma1, const double *rms,
                   const double *thresholds, double rms_max, uint8_t *detected, void *stream);
+
+/*
+ * Interior-point kernel choice.  Every family below is a complete
+ * implementation of the same solve (Sec. 2.2); they differ in how a pixel's
+ * Newton matrix is mapped onto the GPU, and which is fastest depends on the
+ * library size.  Without a choice, a library of N uses the first family
+ * compiled for its padded size NC in the order ROWCYCLIC, TILE, GROUP (FP64
+ * kernels: the FP64 path and the mixed form's second stage) or TILE32,
+ * GROUP (the mixed form's FP32 stage).  A tuning table measured on the
+ * device (paper_1402_2518_amd/autotune.py) installs its choices here.
+ */
+#define LINMIN_KERNEL_DEFAULT 0   /* the rule above */
+#define LINMIN_KERNEL_ROWCYCLIC 1 /* FP64, one pixel per wavefront, 4x4x4 FP64 matrix cores */
+#define LINMIN_KERNEL_TILE 2      /* FP64, four pixels per wavefront, 4x4x4 FP64 matrix cores */
+#define LINMIN_KERNEL_GROUP 3     /* FP64 or FP32, a group of lanes per pixel, vector units */
+#define LINMIN_KERNEL_TILE32 4    /* FP32, sixteen pixels per wavefront, 4x4x1 FP32 matrix cores */
+#define LINMIN_STAGE_FP64 0       /* the FP64 interior-point kernels */
+#define LINMIN_STAGE_FP32 1       /* the FP32 stage of LINMIN_MIXED */
+
+/*
+ * Use family for the interior-point solves of stage for every library whose
+ * padded size equals that of a library of N (1 <= N <= LINMIN_N_MAX), in
+ * this process, for unmix calls enqueued and batches created afterwards
+ * (work already enqueued is not affected; safe to call from any thread).
+ * LINMIN_KERNEL_DEFAULT restores the rule.  Errors: EINVAL (N or stage out
+ * of range), EUNSUPPORTED (family not compiled for that size and stage).
+ */
+int linmin_set_kernel(int N, int stage, int family);
+
+/* The family a library of N uses for stage now (a LINMIN_KERNEL_* value
+ * other than DEFAULT), or EINVAL. */
+int linmin_get_kernel(int N, int stage);
 
 /* Release a library (after all work using it has completed). */
 int linmin_destroy_library(linmin_lib lib);

@@ -33,6 +33,11 @@ def tiles():
     return re.findall(r"^LM_TILE\((\d+)\)", txt, re.M)
 
 
+def tile32s():
+    txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
+    return re.findall(r"^LM_TILE32\((\d+)\)", txt, re.M)
+
+
 def rc_tiles():
     txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
     return re.findall(r"^LM_RC\((\d+)\)", txt, re.M)
@@ -57,6 +62,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for t in tiles():
         units.append((os.path.join(CSRC, "ipm_tile.hip"), os.path.join(BUILD, f"ipm_tile_{t}.o"),
                       (f"-DLM_TILE_T={t}",)))
+    for t in tile32s():
+        units.append((os.path.join(CSRC, "ipm_tile32.hip"), os.path.join(BUILD, f"ipm_tile32_{t}.o"),
+                      (f"-DLM_TILE32_T={t}",)))
     for t in rc_tiles():
         units.append((os.path.join(CSRC, "ipm_rc.hip"), os.path.join(BUILD, f"ipm_rc_{t}.o"),
                       (f"-DLM_RC_T={t}",)))

@@ -307,6 +307,7 @@ __device__ __forceinline__ void ipm_body(const IpmParams& prm, int64_t blk) {
   bool sfree = pos;    // finishing step: no sum row (slack free or no sum constraint)
   uint32_t freem = 0;  // finishing step: bit s set when row s*G+t is free
   int kp = 0;          // finishing-step corrections so far
+  bool stalled = false;  // first stage of the mixed form: the last step was too short
   T pa[S], pnu = T(0);
 
   T g[S], rd[S], D[S], x[S], dla[S];
@@ -329,7 +330,7 @@ __device__ __forceinline__ void ipm_body(const IpmParams& prm, int64_t blk) {
       rdm = gmax<G>(rdm);
       bool conv;
       if constexpr (MODE == kStage1)
-        conv = mu <= tol_mu;
+        conv = mu <= tol_mu || stalled || it >= kStage1MaxIt;
       else
         conv = mu <= tol_mu && rdm <= tol_d * (T(1) + bhmax) && fabs(rp) <= tol_p;
       if (conv) {
@@ -480,6 +481,7 @@ __device__ __forceinline__ void ipm_body(const IpmParams& prm, int64_t blk) {
           if (xN < T(0)) step = fmin(step, -nu / xN);
         }
         const T alpha = fmin(T(1), eta * step);
+        if constexpr (MODE == kStage1) stalled = !(alpha >= T(kStage1MinStep));
         if (phase == kIpm && finite(alpha)) {
           static_for<0, S>([&](auto ss) {
             a[ss] = fmaT(alpha, x[ss], a[ss]);

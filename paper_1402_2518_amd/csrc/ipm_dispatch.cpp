@@ -1,6 +1,20 @@
-// ipm_dispatch.cpp -- choose the compiled interior-point shape for a library.
+// ipm_dispatch.cpp -- choose the compiled interior-point kernel for a library.
+//
+// Kernel families (every one a complete implementation of the same method):
+//   row-cyclic  FP64, one pixel per wavefront on the 4x4x4 FP64 matrix cores
+//   tile        FP64, four pixels per wavefront on the 4x4x4 FP64 matrix cores
+//   group       FP64 or FP32, a group of lanes per pixel on the vector units
+//   tile32      FP32 (first stage of the mixed form), sixteen pixels per
+//               wavefront on the 4x4x1 FP32 matrix cores
+// The default choice per padded size NC is the first family compiled for it
+// in the order above (FP32: tile32, then group).  A measured table installed
+// with linmin_set_kernel_choice overrides it where the chosen family exists
+// for NC; LINMIN_FP64_KERNEL=valu|tile and LINMIN_FP32_KERNEL=valu force a
+// family for comparison runs.
 #include <stdlib.h>
 #include <string.h>
+
+#include <atomic>
 
 #include "kernels.h"
 
@@ -10,10 +24,12 @@ namespace lm {
   int ipm_entry_##t##_##nc##_##g(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_TILE(t) int ipm_tile_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_RC(t) int ipm_rc_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
+#define LM_TILE32(t) int ipm_tile32_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
+#undef LM_TILE32
 
 int ipm_shape_nc(int n) {
   int best = -1;
@@ -21,51 +37,13 @@ int ipm_shape_nc(int n) {
   if (nc >= n && (best < 0 || nc < best)) best = nc;
 #define LM_TILE(t)
 #define LM_RC(t)
+#define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
+#undef LM_TILE32
   return best;
-}
-
-// FP64 kernel family: the row-cyclic matrix-core kernel (one pixel per
-// wavefront) where such a shape exists for NC, else the four-pixel tile
-// kernel, else the lane-group kernel.  LINMIN_FP64_KERNEL=tile skips the
-// row-cyclic shapes and =valu forces the lane-group kernel (all three are
-// complete implementations; the switch exists to compare them).
-static int forced_family() {
-  static int forced = -1;
-  if (forced < 0) {
-    const char* e = getenv("LINMIN_FP64_KERNEL");
-    forced = (e && strcmp(e, "valu") == 0) ? 1 : ((e && strcmp(e, "tile") == 0) ? 2 : 0);
-  }
-  return forced;
-}
-
-static bool use_rc(int nc) {
-  if (forced_family() != 0 || nc % 16) return false;
-  bool have = false;
-#define LM_SHAPE(t, nc_, g)
-#define LM_TILE(t)
-#define LM_RC(t) have |= (4 * t == nc);
-#include "ipm_shapes.def"
-#undef LM_SHAPE
-#undef LM_TILE
-#undef LM_RC
-  return have;
-}
-
-static bool use_tile(int nc) {
-  if (forced_family() == 1 || nc % 4) return false;
-  bool have = false;
-#define LM_SHAPE(t, nc_, g)
-#define LM_TILE(t) have |= (4 * t == nc);
-#define LM_RC(t)
-#include "ipm_shapes.def"
-#undef LM_SHAPE
-#undef LM_TILE
-#undef LM_RC
-  return have;
 }
 
 // lanes per pixel of the lane-group shape for (nc, precision), or -1
@@ -74,61 +52,177 @@ static int group_lanes(int nc, bool fp32) {
   if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return g;
 #define LM_TILE(t)
 #define LM_RC(t)
+#define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
+#undef LM_TILE32
   return -1;
+}
+
+bool ipm_family_available(int nc, bool fp32, int fam) {
+  bool have = false;
+  switch (fam) {
+    case kFamRowCyclic:
+      if (fp32 || nc % 16) return false;
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t)
+#define LM_RC(t) have |= (4 * t == nc);
+#define LM_TILE32(t)
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+#undef LM_RC
+#undef LM_TILE32
+      return have;
+    case kFamTile:
+      if (fp32 || nc % 4) return false;
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t) have |= (4 * t == nc);
+#define LM_RC(t)
+#define LM_TILE32(t)
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+#undef LM_RC
+#undef LM_TILE32
+      return have;
+    case kFamTile32:
+      if (!fp32 || nc % 4) return false;
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t)
+#define LM_RC(t)
+#define LM_TILE32(t) have |= (4 * t == nc);
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+#undef LM_RC
+#undef LM_TILE32
+      return have;
+    case kFamGroup:
+      return group_lanes(nc, fp32) > 0;
+  }
+  return false;
+}
+
+// measured choices: [fp32][nc], 0 = none (the default rule applies)
+static std::atomic<int> g_choice[2][kNcMax + 1];
+
+int ipm_set_family(int nc, bool fp32, int fam) {
+  if (nc < 1 || nc > kNcMax) return -1;
+  if (fam != 0 && !ipm_family_available(nc, fp32, fam)) return -1;
+  g_choice[fp32 ? 1 : 0][nc].store(fam, std::memory_order_relaxed);
+  return 0;
+}
+
+static int forced_family(bool fp32) {
+  static int forced64 = -1, forced32 = -1;
+  if (forced64 < 0) {
+    const char* e = getenv("LINMIN_FP64_KERNEL");
+    forced64 = (e && strcmp(e, "valu") == 0) ? kFamGroup : ((e && strcmp(e, "tile") == 0) ? kFamTile : 0);
+    const char* f = getenv("LINMIN_FP32_KERNEL");
+    forced32 = (f && strcmp(f, "valu") == 0) ? kFamGroup : 0;
+  }
+  return fp32 ? forced32 : forced64;
+}
+
+int ipm_family(int nc, bool fp32) {
+  const int forced = forced_family(fp32);
+  if (forced && ipm_family_available(nc, fp32, forced)) return forced;
+  if (nc >= 1 && nc <= kNcMax) {
+    const int t = g_choice[fp32 ? 1 : 0][nc].load(std::memory_order_relaxed);
+    if (t && ipm_family_available(nc, fp32, t)) return t;
+  }
+  static const int order64[] = {kFamRowCyclic, kFamTile, kFamGroup};
+  static const int order32[] = {kFamTile32, kFamGroup};
+  if (fp32) {
+    for (int f : order32)
+      if (ipm_family_available(nc, true, f)) return f;
+  } else {
+    for (int f : order64)
+      if (ipm_family_available(nc, false, f)) return f;
+  }
+  return 0;
 }
 
 int ipm_kernel_class(int n, bool fp32, bool stable) {
   const int nc = ipm_shape_nc(n);
   if (nc < 0) return -1;
-  if (!fp32 && use_rc(nc)) return 5000 + nc;
-  if (!fp32 && use_tile(nc)) return (stable ? 4000 : 1000) + nc;
-  return group_lanes(nc, fp32) > 0 ? (fp32 ? 3000 : 2000) + nc : -1;
+  switch (ipm_family(nc, fp32)) {
+    case kFamRowCyclic: return 5000 + nc;
+    case kFamTile: return (stable ? 4000 : 1000) + nc;
+    case kFamTile32: return 6000 + nc;
+    case kFamGroup: return (fp32 ? 3000 : 2000) + nc;
+  }
+  return -1;
 }
 
 int ipm_pixels_per_block(int n, bool fp32) {
   const int nc = ipm_shape_nc(n);
   if (nc < 0) return -1;
-  if (!fp32 && use_rc(nc)) return 4;    // one pixel per wavefront, four wavefronts
-  if (!fp32 && use_tile(nc)) return 16;  // four pixels per wavefront, four wavefronts
-  const int g = group_lanes(nc, fp32);
-  return g > 0 ? 4 * (64 / g) : -1;
+  switch (ipm_family(nc, fp32)) {
+    case kFamRowCyclic: return 4;   // one pixel per wavefront, four wavefronts
+    case kFamTile: return 16;       // four pixels per wavefront, four wavefronts
+    case kFamTile32: return 64;     // sixteen pixels per wavefront, four wavefronts
+    case kFamGroup: return 4 * (64 / group_lanes(nc, fp32));
+  }
+  return -1;
 }
 
 static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool fp32, hipStream_t st) {
   const int nc = ipm_shape_nc(n);
   if (nc < 0) return -5;
-  if (!fp32 && use_rc(nc)) {
+  switch (ipm_family(nc, fp32)) {
+    case kFamRowCyclic:
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
 #define LM_RC(t) \
-    if (4 * t == nc) return ipm_rc_entry_##t(p, b, mode, st);
+      if (4 * t == nc) return ipm_rc_entry_##t(p, b, mode, st);
+#define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
-  }
-  if (!fp32 && use_tile(nc)) {
+#undef LM_TILE32
+      break;
+    case kFamTile:
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t) \
-    if (4 * t == nc) return ipm_tile_entry_##t(p, b, mode, st);
+      if (4 * t == nc) return ipm_tile_entry_##t(p, b, mode, st);
 #define LM_RC(t)
+#define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
-  }
-#define LM_SHAPE(t, nc_, g)                                              \
-  if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return ipm_entry_##t##_##nc_##_##g(p, b, mode, st);
+#undef LM_TILE32
+      break;
+    case kFamTile32:
+#define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
 #define LM_RC(t)
+#define LM_TILE32(t) \
+      if (4 * t == nc) return ipm_tile32_entry_##t(p, b, mode, st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
+#undef LM_TILE32
+      break;
+    case kFamGroup:
+#define LM_SHAPE(t, nc_, g) \
+      if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return ipm_entry_##t##_##nc_##_##g(p, b, mode, st);
+#define LM_TILE(t)
+#define LM_RC(t)
+#define LM_TILE32(t)
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+#undef LM_RC
+#undef LM_TILE32
+      break;
+  }
   return -5;
 }
 

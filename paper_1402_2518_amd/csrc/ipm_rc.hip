@@ -32,6 +32,10 @@ constexpr int kRowRor8 = 0x128;  // block b <- block b - 2
 
 template <int T>
 struct RC {
+  using real = double;
+  using xreg = double;
+  static constexpr bool kCompact = false;
+  static constexpr bool kRecomputeGrad = false;
   static_assert(T % 4 == 0, "row-cyclic tiles need a multiple of four tile rows");
   static constexpr int R = T / 4;                 // row slots per block
   static constexpr int NP = 4 * T;                // padded library size

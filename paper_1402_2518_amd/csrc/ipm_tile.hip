@@ -63,6 +63,10 @@ __device__ __forceinline__ int bor_i(int v) {
 
 template <int T, bool ST>
 struct Tile {
+  using real = double;
+  using xreg = double;
+  static constexpr bool kCompact = false;
+  static constexpr bool kRecomputeGrad = false;
   static constexpr int NP = 4 * T;
   static constexpr int C = (T + 3) / 4;  // compact slots
   static constexpr int NX = T;           // solve registers: one per tile row

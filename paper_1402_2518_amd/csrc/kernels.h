@@ -68,6 +68,20 @@ struct IpmBatch {
   int64_t blocks;         // total workgroups of the launch
 };
 
+// The FP32 stage of the mixed form also hands its iterate over after this
+// many steps, or after a step shorter than this fraction of the way to the
+// boundary: the single-precision Newton directions have stopped making
+// progress, and the FP64 stage continues from the last accepted iterate.
+constexpr int kStage1MaxIt = 60;
+constexpr double kStage1MinStep = 1e-3;
+
+// Interior-point kernel families (ipm_dispatch.cpp).
+enum : int { kFamRowCyclic = 1, kFamTile = 2, kFamGroup = 3, kFamTile32 = 4 };
+constexpr int kNcMax = 128;
+bool ipm_family_available(int nc, bool fp32, int fam);
+int ipm_family(int nc, bool fp32);                   // family used for padded size nc
+int ipm_set_family(int nc, bool fp32, int fam);      // 0 = default rule; -1 if not available
+
 // ipm_dispatch.cpp: picks the compiled shape for n and precision.
 int ipm_shape_nc(int n);                      // padded size NC used for a library of size n
 int ipm_pixels_per_block(int n, bool fp32);   // pixels of one workgroup for that shape

@@ -264,7 +264,7 @@ void linmin_default_opts(linmin_opts* o) {
   o->lambda0 = 0.1;
   o->tau = 1e-11;
   o->deg_tol = 1e-9;
-  o->mu_switch = 1e-7;
+  o->mu_switch = 1e-8;
   o->status = nullptr;
   o->iters = nullptr;
   o->objective = nullptr;
@@ -283,6 +283,24 @@ const char* linmin_strerror(int code) {
     case LINMIN_ESCRATCH: return "work area larger than the no-allocation scratch array";
     default: return "unknown error";
   }
+}
+
+int linmin_set_kernel(int N, int stage, int family) {
+  if (N < 1 || N > LINMIN_N_MAX || (stage != LINMIN_STAGE_FP64 && stage != LINMIN_STAGE_FP32)) return LINMIN_EINVAL;
+  if (family < LINMIN_KERNEL_DEFAULT || family > LINMIN_KERNEL_TILE32) return LINMIN_EINVAL;
+  const int nc = lm::ipm_shape_nc(N);
+  if (nc < 0) return LINMIN_EUNSUPPORTED;
+  static_assert(LINMIN_KERNEL_ROWCYCLIC == lm::kFamRowCyclic && LINMIN_KERNEL_TILE == lm::kFamTile &&
+                    LINMIN_KERNEL_GROUP == lm::kFamGroup && LINMIN_KERNEL_TILE32 == lm::kFamTile32,
+                "kernel family codes");
+  return lm::ipm_set_family(nc, stage == LINMIN_STAGE_FP32, family) == 0 ? LINMIN_OK : LINMIN_EUNSUPPORTED;
+}
+
+int linmin_get_kernel(int N, int stage) {
+  if (N < 1 || N > LINMIN_N_MAX || (stage != LINMIN_STAGE_FP64 && stage != LINMIN_STAGE_FP32)) return LINMIN_EINVAL;
+  const int nc = lm::ipm_shape_nc(N);
+  if (nc < 0) return LINMIN_EUNSUPPORTED;
+  return lm::ipm_family(nc, stage == LINMIN_STAGE_FP32);
 }
 
 int linmin_extra_spectra(int L, int n_extra, const double* wavelengths, float* out) {

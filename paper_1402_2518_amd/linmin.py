@@ -21,6 +21,11 @@ COV_NONE, COV_FULL, COV_PACKED, COV_DIAG = 0, 1, 2, 3
 STO, SLO, POS = 0, 1, 2  # sum-to-one, sum-lower-than-one, positivity only
 PX_MAXIT, PX_NONFINITE, PX_BAD_SIGMA, PX_NOT_PD, PX_DEGENERATE, PX_INEXACT = 1, 2, 4, 8, 16, 32
 N_MAX = 128
+# interior-point kernel families and stages (linmin_set_kernel)
+KERNEL_DEFAULT, KERNEL_ROWCYCLIC, KERNEL_TILE, KERNEL_GROUP, KERNEL_TILE32 = 0, 1, 2, 3, 4
+STAGE_FP64, STAGE_FP32 = 0, 1
+KERNELS = {"default": KERNEL_DEFAULT, "rowcyclic": KERNEL_ROWCYCLIC, "tile": KERNEL_TILE, "group": KERNEL_GROUP,
+           "tile32": KERNEL_TILE32}
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # LINMIN_NOALLOC_SCRATCH_BYTES
 
@@ -28,7 +33,8 @@ EXPORTS = ("linmin_default_opts", "linmin_create_library", "linmin_unmix", "linm
            "linmin_workspace_bytes",
            "linmin_library_info", "linmin_library_gram", "linmin_destroy_library", "linmin_strerror",
            "linmin_extra_spectra", "linmin_batch_create", "linmin_batch_run", "linmin_batch_device_bytes",
-           "linmin_batch_destroy", "linmin_error_maps", "linmin_thresholds", "linmin_detect")
+           "linmin_batch_destroy", "linmin_error_maps", "linmin_thresholds", "linmin_detect",
+           "linmin_set_kernel", "linmin_get_kernel")
 
 
 class Opts(ctypes.Structure):
@@ -98,6 +104,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.linmin_thresholds.restype = ctypes.c_int
         lib.linmin_detect.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, dbl, vp, vp]
         lib.linmin_detect.restype = ctypes.c_int
+        lib.linmin_set_kernel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.linmin_set_kernel.restype = ctypes.c_int
+        lib.linmin_get_kernel.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.linmin_get_kernel.restype = ctypes.c_int
         lib.linmin_strerror.argtypes = [ctypes.c_int]
         lib.linmin_strerror.restype = ctypes.c_char_p
         _lib = lib
@@ -106,6 +116,24 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 
 def strerror(code: int) -> str:
     return load().linmin_strerror(int(code)).decode()
+
+
+def set_kernel(N: int, stage: int, family) -> None:
+    """Interior-point kernel family for libraries of (padded) size N in this
+    process (``linmin_set_kernel``); ``family`` is a name of ``KERNELS`` or
+    its code."""
+    fam = KERNELS[family] if isinstance(family, str) else int(family)
+    rc = load().linmin_set_kernel(int(N), int(stage), fam)
+    if rc != OK:
+        raise LinminError(rc, "linmin_set_kernel")
+
+
+def get_kernel(N: int, stage: int) -> int:
+    """Family a library of N uses for ``stage`` now (``linmin_get_kernel``)."""
+    rc = load().linmin_get_kernel(int(N), int(stage))
+    if rc < 0:
+        raise LinminError(rc, "linmin_get_kernel")
+    return rc
 
 
 def default_opts(**kw) -> Opts:

@@ -78,7 +78,7 @@ def test_strerror_and_defaults_without_gpu():
     assert lib.linmin_strerror(-4).decode().startswith("matrix not")
     o = linmin.default_opts()
     assert o.maxit == 200 and o.tol_mu == 1e-13 and o.precision == linmin.FP64
-    assert o.mu_switch == 1e-7
+    assert o.mu_switch == 1e-8
     assert o.constraint == linmin.STO
     h = ctypes.c_void_p()
     # argument errors are reported before any device work
@@ -113,3 +113,34 @@ def test_job_struct_layout():
     # linmin_job: library handle, cube, P, sigma, then five output pointers
     assert ctypes.sizeof(linmin.Job) == 9 * 8
     assert linmin.Job.P.offset == 16
+
+
+def test_kernel_choice_without_gpu():
+    # the choice of interior-point kernel family is host state only
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"#define (LINMIN_\w+) \(?(-?\d+)u?\)?", txt))
+    assert (int(defs["LINMIN_KERNEL_ROWCYCLIC"]), int(defs["LINMIN_KERNEL_TILE"]), int(defs["LINMIN_KERNEL_GROUP"]),
+            int(defs["LINMIN_KERNEL_TILE32"])) == (linmin.KERNEL_ROWCYCLIC, linmin.KERNEL_TILE,
+                                                  linmin.KERNEL_GROUP, linmin.KERNEL_TILE32)
+    assert (int(defs["LINMIN_STAGE_FP64"]), int(defs["LINMIN_STAGE_FP32"])) == (linmin.STAGE_FP64, linmin.STAGE_FP32)
+    lib = linmin.load()
+    # default rule: matrix cores first
+    assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_TILE
+    assert linmin.get_kernel(96, linmin.STAGE_FP64) == linmin.KERNEL_ROWCYCLIC
+    assert linmin.get_kernel(36, linmin.STAGE_FP32) == linmin.KERNEL_TILE32
+    assert linmin.get_kernel(64, linmin.STAGE_FP32) == linmin.KERNEL_GROUP
+    try:
+        linmin.set_kernel(33, linmin.STAGE_FP64, "group")  # same padded size as 36
+        assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_GROUP
+        assert linmin.get_kernel(32, linmin.STAGE_FP64) == linmin.KERNEL_TILE
+    finally:
+        linmin.set_kernel(36, linmin.STAGE_FP64, "default")
+    assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_TILE
+    # not compiled for that size or stage; out of range
+    assert lib.linmin_set_kernel(96, linmin.STAGE_FP32, linmin.KERNEL_TILE32) == linmin.EUNSUPPORTED
+    assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_TILE) == linmin.EUNSUPPORTED
+    assert lib.linmin_set_kernel(0, linmin.STAGE_FP64, 0) == linmin.EINVAL
+    assert lib.linmin_set_kernel(129, linmin.STAGE_FP64, 0) == linmin.EINVAL
+    assert lib.linmin_set_kernel(36, 2, 0) == linmin.EINVAL
+    assert lib.linmin_set_kernel(36, linmin.STAGE_FP64, 9) == linmin.EINVAL
+    assert lib.linmin_get_kernel(36, 5) == linmin.EINVAL

@@ -159,6 +159,28 @@ def test_library_sizes(dev, N):
                  f_tol=1e-9 if precision == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("N", [8, 21, 36])
+def test_fp32_stage_kernel_families(dev, N):
+    """The mixed form's FP32 stage on each kernel family compiled for the
+    size (the 4x4x1 matrix-core tiles and the lane groups): both hand an
+    iterate to the same FP64 stage, so both must meet the oracle."""
+    from paper_1402_2518_amd import linmin
+    _say(f"[gpu] FP32 stage kernel families N={N}")
+    w = synth.custom_workload(N, 96, 1203, seed=700 + N, n_extra=4, k_max=4)
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    r = oracle.unmix(S, X, s)
+    assert linmin.get_kernel(N, linmin.STAGE_FP32) == linmin.KERNEL_TILE32
+    try:
+        for fam in ("tile32", "group"):
+            linmin.set_kernel(N, linmin.STAGE_FP32, fam)
+            g = _gpu(S, X, s, dev, precision="mixed")
+            _compare(g, r, S, X, a_tol=1e-3, f_tol=1e-4)
+            _say(f"[gpu]   {fam}: iters {g['iters'].mean():.2f}")
+    finally:
+        linmin.set_kernel(N, linmin.STAGE_FP32, "default")
+
+
 def test_cycling_pixels_converge(dev):
     _say("[gpu] orbital pixels that make plain Mehrotra cycle")
     from test_oracle import cycling_pixels
