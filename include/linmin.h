@@ -243,8 +243,10 @@ typedef struct linmin_batch_s *linmin_batch;
 /*
  * Plan a batch.  Synchronous on the current device: checks every job,
  * groups the cubes by compiled kernel (projection width, interior-point
- * shape), allocates the work areas of all cubes in one device buffer and
- * uploads one job table per launch.  Afterwards linmin_batch_run enqueues
+ * kernel as linmin_set_kernel has chosen it at this moment), allocates the
+ * work areas of all cubes in one device buffer, uploads one job table per
+ * launch and creates up to three streams and four events of the batch's own
+ * (default priority).  Afterwards linmin_batch_run enqueues
  * the fused launches only: no allocation, no host-to-device copy, so a run
  * may be captured in a HIP graph.
  *   jobs, n_jobs  host array of n_jobs >= 0 jobs (copied; the buffers they
@@ -263,9 +265,13 @@ int linmin_batch_create(const linmin_job *jobs, int n_jobs, const linmin_opts *o
 /*
  * Enqueue every job of the batch on stream (NULL: the default stream):
  * projections, interior-point solves and covariance, each stage as one
- * launch per compiled shape over all cubes of that shape.  Asynchronous like
- * a kernel launch.  Runs of one batch share its work areas: two runs in
- * flight at once on different streams race.  Errors: EINVAL (NULL batch,
+ * launch per compiled shape over all cubes of that shape.  The
+ * interior-point launches of different library sizes run concurrently on
+ * the batch's streams, forked from stream after the projections and joined
+ * back to it before the covariance (events only, so a run captured from
+ * stream into a HIP graph captures the fork and the join).  Asynchronous
+ * like a kernel launch.  Runs of one batch share its work areas and
+ * streams: two runs in flight at once race.  Errors: EINVAL (NULL batch,
  * other device current), EHIP.
  */
 int linmin_batch_run(linmin_batch batch, void *stream);
@@ -333,15 +339,18 @@ int linmin_detect(int N, int64_t P, const double *coeffs, const double *sigma1, 
  * Use family for the interior-point solves of stage for every library whose
  * padded size equals that of a library of N (1 <= N <= LINMIN_N_MAX), in
  * this process, for unmix calls enqueued and batches created afterwards
- * (work already enqueued is not affected; safe to call from any thread).
- * LINMIN_KERNEL_DEFAULT restores the rule.  Errors: EINVAL (N or stage out
- * of range), EUNSUPPORTED (family not compiled for that size and stage).
+ * (work already enqueued and batches already created keep their kernels;
+ * safe to call from any thread).  lanes: for LINMIN_KERNEL_GROUP the lanes
+ * per pixel (0 = the default width), else 0.  LINMIN_KERNEL_DEFAULT
+ * restores the rule.  Errors: EINVAL (N, stage, family or lanes out of
+ * range), EUNSUPPORTED (that kernel is not compiled for the size and stage).
  */
-int linmin_set_kernel(int N, int stage, int family);
+int linmin_set_kernel(int N, int stage, int family, int lanes);
 
 /* The family a library of N uses for stage now (a LINMIN_KERNEL_* value
- * other than DEFAULT), or EINVAL. */
-int linmin_get_kernel(int N, int stage);
+ * other than DEFAULT), with its group width in *lanes (0 for the other
+ * families; lanes may be NULL), or EINVAL. */
+int linmin_get_kernel(int N, int stage, int *lanes);
 
 /* Release a library (after all work using it has completed). */
 int linmin_destroy_library(linmin_lib lib);

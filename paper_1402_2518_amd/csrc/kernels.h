@@ -79,17 +79,24 @@ constexpr double kStage1MinStep = 1e-3;
 enum : int { kFamRowCyclic = 1, kFamTile = 2, kFamGroup = 3, kFamTile32 = 4 };
 constexpr int kNcMax = 128;
 bool ipm_family_available(int nc, bool fp32, int fam);
+bool ipm_family_available(int nc, bool fp32, int fam, int lanes);  // lanes: group width, 0 = default
 int ipm_family(int nc, bool fp32);                   // family used for padded size nc
-int ipm_set_family(int nc, bool fp32, int fam);      // 0 = default rule; -1 if not available
+int ipm_group_lanes(int nc, bool fp32);              // width of the group kernel used for nc
+int ipm_set_family(int nc, bool fp32, int fam, int lanes);  // fam 0 = default rule; -1 if not compiled
 
 // ipm_dispatch.cpp: picks the compiled shape for n and precision.
 int ipm_shape_nc(int n);                      // padded size NC used for a library of size n
-int ipm_pixels_per_block(int n, bool fp32);   // pixels of one workgroup for that shape
+int ipm_choice_code(int n, bool fp32);        // kernel used now: family | group width << 8
+int ipm_pixels_per_block(int n, bool fp32);   // pixels of one workgroup for that kernel
+int ipm_pixels_per_block_code(int code);
 int ipm_kernel_class(int n, bool fp32, bool stable);  // launches of equal class can share a batch
+int ipm_kernel_class_of(int n, bool fp32, bool stable, int code);  // the same for kernel code
 int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st);
 // batched: every job of b has a library with ipm_kernel_class(n, fp32,
-// stable) equal to that of n; constraint and stable as in IpmParams
-int launch_ipm_batch(int n, int constraint, int stable, const IpmBatch& b, int mode, bool fp32, hipStream_t st);
+// stable) equal to that of n, planned for the kernel code names (fixed when
+// the batch was planned); constraint and stable as in IpmParams
+int launch_ipm_batch(int n, int constraint, int stable, const IpmBatch& b, int mode, bool fp32, int code,
+                     hipStream_t st);
 
 // gemm.hip
 // One cube of a batched projection launch: bh = Y W (and c = y^T y, or

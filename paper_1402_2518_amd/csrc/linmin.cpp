@@ -12,6 +12,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <new>
 #include <vector>
@@ -285,22 +286,24 @@ const char* linmin_strerror(int code) {
   }
 }
 
-int linmin_set_kernel(int N, int stage, int family) {
+int linmin_set_kernel(int N, int stage, int family, int lanes) {
   if (N < 1 || N > LINMIN_N_MAX || (stage != LINMIN_STAGE_FP64 && stage != LINMIN_STAGE_FP32)) return LINMIN_EINVAL;
-  if (family < LINMIN_KERNEL_DEFAULT || family > LINMIN_KERNEL_TILE32) return LINMIN_EINVAL;
+  if (family < LINMIN_KERNEL_DEFAULT || family > LINMIN_KERNEL_TILE32 || lanes < 0 || lanes > 64) return LINMIN_EINVAL;
+  if (lanes != 0 && family != LINMIN_KERNEL_GROUP) return LINMIN_EINVAL;
   const int nc = lm::ipm_shape_nc(N);
   if (nc < 0) return LINMIN_EUNSUPPORTED;
   static_assert(LINMIN_KERNEL_ROWCYCLIC == lm::kFamRowCyclic && LINMIN_KERNEL_TILE == lm::kFamTile &&
                     LINMIN_KERNEL_GROUP == lm::kFamGroup && LINMIN_KERNEL_TILE32 == lm::kFamTile32,
                 "kernel family codes");
-  return lm::ipm_set_family(nc, stage == LINMIN_STAGE_FP32, family) == 0 ? LINMIN_OK : LINMIN_EUNSUPPORTED;
+  return lm::ipm_set_family(nc, stage == LINMIN_STAGE_FP32, family, lanes) == 0 ? LINMIN_OK : LINMIN_EUNSUPPORTED;
 }
 
-int linmin_get_kernel(int N, int stage) {
+int linmin_get_kernel(int N, int stage, int* lanes) {
   if (N < 1 || N > LINMIN_N_MAX || (stage != LINMIN_STAGE_FP64 && stage != LINMIN_STAGE_FP32)) return LINMIN_EINVAL;
-  const int nc = lm::ipm_shape_nc(N);
-  if (nc < 0) return LINMIN_EUNSUPPORTED;
-  return lm::ipm_family(nc, stage == LINMIN_STAGE_FP32);
+  const int code = lm::ipm_choice_code(N, stage == LINMIN_STAGE_FP32);
+  if (code < 0) return LINMIN_EUNSUPPORTED;
+  if (lanes) *lanes = code >> 8;
+  return code & 0xff;
 }
 
 int linmin_extra_spectra(int L, int n_extra, const double* wavelengths, float* out) {
@@ -486,10 +489,20 @@ struct linmin_batch_s {
   struct Ipm {
     int n, mode, stable;
     bool fp32;
+    int code;  // kernel (family | group width << 8), fixed at planning
     lm::IpmBatch b;
+    int lane = 0;  // 0: the caller's stream; k > 0: side stream k - 1
   };
   std::vector<Ipm> ipm;  // in launch order
   lm::CovBatch cov[3]{};
+  // interior-point groups of different library sizes are independent: they
+  // run on up to kLanes streams at once (forked from and joined back to the
+  // caller's stream with events), so small groups fill the device beside
+  // the largest one
+  static constexpr int kLanes = 4;
+  int lanes = 1;
+  hipStream_t side[kLanes - 1] = {};
+  hipEvent_t fork = nullptr, join[kLanes - 1] = {};
 };
 
 namespace {
@@ -576,7 +589,8 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   std::map<int, Group<lm::ProjJob>> proj;  // by column blocks
   Group<lm::ProjJob> quad;
   std::map<int, Group<lm::IpmParams>> ipm1, ipm2;  // by kernel class: FP64 (or stage 2), FP32 stage 1
-  std::map<int, int> class_n1, class_n2;           // a library size of each class
+  std::map<int, std::pair<int, int>> class_n1, class_n2;  // a library size of each class, its kernel code
+  std::map<int, int> code1, code2;                         // kernel code per library size
   Group<lm::CovJob> cov[3];
   int qcap = 0;
   for (int j = 0; j < n_jobs; ++j) {
@@ -596,15 +610,19 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
     if (lib->Ci) quad.add(pj, cdiv(P, lm::proj_pixels_per_block()));
 
     lm::IpmParams prm = make_ipm(lib, P, J.sigma, J.out_coeffs, status, J.iters, J.objective, o, w, ws, want_cov);
-    const int k2 = lm::ipm_kernel_class(lib->N, false, lib->stable != 0);
+    // the kernel of each stage is fixed here, once per job, so that block
+    // counts and launches agree whatever linmin_set_kernel does later
+    const int c2 = code2.count(lib->N) ? code2[lib->N] : (code2[lib->N] = lm::ipm_choice_code(lib->N, false));
+    const int k2 = lm::ipm_kernel_class_of(lib->N, false, lib->stable != 0, c2);
     prm.Gh = lib->Gh64;
-    ipm2[k2].add(prm, cdiv(P, lm::ipm_pixels_per_block(lib->N, false)));
-    class_n2[k2] = lib->N;
+    ipm2[k2].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c2)));
+    class_n2[k2] = {lib->N, c2};
     if (mixed) {
-      const int k1 = lm::ipm_kernel_class(lib->N, true, lib->stable != 0);
+      const int c1 = code1.count(lib->N) ? code1[lib->N] : (code1[lib->N] = lm::ipm_choice_code(lib->N, true));
+      const int k1 = lm::ipm_kernel_class_of(lib->N, true, lib->stable != 0, c1);
       prm.Gh = lib->Gh32;
-      ipm1[k1].add(prm, cdiv(P, lm::ipm_pixels_per_block(lib->N, true)));
-      class_n1[k1] = lib->N;
+      ipm1[k1].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c1)));
+      class_n1[k1] = {lib->N, c1};
     }
     if (want_cov) {
       const lm::CovJob cj{lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), (double*)at(w.dcorner), J.sigma,
@@ -643,10 +661,11 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   if (!quad.jobs.empty())
     b->quad = {0, (const lm::ProjJob*)(t + quad.jobs_at), (const int64_t*)(t + quad.start_at), (int)quad.jobs.size(),
                quad.units()};
-  auto add_ipm = [&](std::map<int, Group<lm::IpmParams>>& m, std::map<int, int>& nmap, int mode, bool fp32) {
+  auto add_ipm = [&](std::map<int, Group<lm::IpmParams>>& m, std::map<int, std::pair<int, int>>& nmap, int mode,
+                     bool fp32) {
     for (auto& kv : m) {
       const auto& g = kv.second;
-      linmin_batch_s::Ipm e{nmap[kv.first], mode, g.jobs.front().stable, fp32,
+      linmin_batch_s::Ipm e{nmap[kv.first].first, mode, g.jobs.front().stable, fp32, nmap[kv.first].second,
                             {(const lm::IpmParams*)(t + g.jobs_at), (const int64_t*)(t + g.start_at),
                              (int)g.jobs.size(), g.units()}};
       b->ipm.push_back(e);
@@ -663,6 +682,40 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
     if (!g.jobs.empty())
       b->cov[k] = {(const lm::CovJob*)(t + g.jobs_at), (const int64_t*)(t + g.start_at), (int)g.jobs.size(), g.units(),
                    qcap};
+  }
+  // Streams for the interior-point groups: the groups of one padded size
+  // (both stages of the mixed form, both factorisations) stay on one stream
+  // in launch order; sizes are placed largest first on the least loaded
+  // stream, the load being pixels x NC^3 (the factorisation's work).
+  {
+    std::map<int, double> cost;  // by padded size
+    for (const auto& g : b->ipm) {
+      const double nc = lm::ipm_shape_nc(g.n);
+      const double pixels = (double)g.b.blocks * lm::ipm_pixels_per_block_code(g.code);
+      cost[(int)nc] += pixels * nc * nc * nc;
+    }
+    std::vector<std::pair<double, int>> order;
+    for (const auto& kv : cost) order.push_back({kv.second, kv.first});
+    std::sort(order.begin(), order.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    const int lanes = std::min<int>(linmin_batch_s::kLanes, (int)order.size());
+    std::vector<double> load(lanes > 0 ? lanes : 1, 0.0);
+    std::map<int, int> lane_of;
+    for (const auto& [c, nc] : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += c;
+      lane_of[nc] = k;
+    }
+    for (auto& g : b->ipm) g.lane = lane_of[lm::ipm_shape_nc(g.n)];
+    b->lanes = std::max(lanes, 1);
+    bool ok = true;
+    if (b->lanes > 1) ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k + 1 < b->lanes; ++k)
+      ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      linmin_batch_destroy(b);
+      return LINMIN_EHIP;
+    }
   }
   *out = b;
   return LINMIN_OK;
@@ -687,9 +740,21 @@ int linmin_batch_run(linmin_batch b, void* stream) {
   if (rc == LINMIN_OK && b->quad.njobs)
     rc = from_launch(lm::launch_quadform_batch(b->quad.jobs, b->quad.start, b->quad.njobs, b->quad.blocks, st));
   if (rc == LINMIN_OK) rc = mark(1);
+  // fork the side streams off the caller's stream, launch every group on its
+  // stream, join them back
+  const int nside = b->lanes - 1;
+  if (rc == LINMIN_OK && nside > 0) rc = hip_ok(hipEventRecord(b->fork, st));
+  for (int k = 0; rc == LINMIN_OK && k < nside; ++k) rc = hip_ok(hipStreamWaitEvent(b->side[k], b->fork, 0));
   for (size_t i = 0; rc == LINMIN_OK && i < b->ipm.size(); ++i) {
     const auto& g = b->ipm[i];
-    rc = from_launch(lm::launch_ipm_batch(g.n, b->o.constraint, g.stable, g.b, g.mode, g.fp32, st));
+    hipStream_t gs = g.lane == 0 ? st : b->side[g.lane - 1];
+    rc = from_launch(lm::launch_ipm_batch(g.n, b->o.constraint, g.stable, g.b, g.mode, g.fp32, g.code, gs));
+  }
+  for (int k = 0; k < nside; ++k) {
+    // join even after a failed launch, so that no side stream is left forked
+    const int r1 = hip_ok(hipEventRecord(b->join[k], b->side[k]));
+    const int r2 = hip_ok(hipStreamWaitEvent(st, b->join[k], 0));
+    if (rc == LINMIN_OK) rc = r1 != LINMIN_OK ? r1 : r2;
   }
   if (rc == LINMIN_OK) rc = mark(2);
   if (rc == LINMIN_OK) rc = from_launch(lm::launch_cov_batch(b->cov[0], b->cov[1], b->cov[2], st));
@@ -701,6 +766,11 @@ size_t linmin_batch_device_bytes(linmin_batch b) { return b ? b->ws_bytes + b->t
 
 int linmin_batch_destroy(linmin_batch b) {
   if (!b) return LINMIN_EINVAL;
+  for (int k = 0; k + 1 < linmin_batch_s::kLanes; ++k) {
+    if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   (void)hipFree(b->ws);
   (void)hipFree(b->tab);
   delete b;

@@ -62,8 +62,14 @@ class LinminError(RuntimeError):
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load the HIP library (raises if it has not been built)."""
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+def load(path: str = LIB_PATH, tuning: bool = True) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built).  On the first
+    load, the measured kernel choices of ``tuning.json`` (written by
+    :mod:`paper_1402_2518_amd.autotune`) are installed, unless ``tuning`` is
+    false or the environment sets ``LINMIN_TUNING=0``."""
     global _lib
     if _lib is None:
         if not os.path.exists(path):
@@ -104,13 +110,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.linmin_thresholds.restype = ctypes.c_int
         lib.linmin_detect.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, dbl, vp, vp]
         lib.linmin_detect.restype = ctypes.c_int
-        lib.linmin_set_kernel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.linmin_set_kernel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.linmin_set_kernel.restype = ctypes.c_int
-        lib.linmin_get_kernel.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.linmin_get_kernel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         lib.linmin_get_kernel.restype = ctypes.c_int
         lib.linmin_strerror.argtypes = [ctypes.c_int]
         lib.linmin_strerror.restype = ctypes.c_char_p
         _lib = lib
+        if tuning and os.environ.get("LINMIN_TUNING", "1") != "0" and os.path.exists(TUNING_PATH):
+            from . import autotune
+            autotune.install(TUNING_PATH)
     return _lib
 
 
@@ -118,22 +127,29 @@ def strerror(code: int) -> str:
     return load().linmin_strerror(int(code)).decode()
 
 
-def set_kernel(N: int, stage: int, family) -> None:
-    """Interior-point kernel family for libraries of (padded) size N in this
-    process (``linmin_set_kernel``); ``family`` is a name of ``KERNELS`` or
-    its code."""
+def set_kernel(N: int, stage: int, family, lanes: int = 0) -> None:
+    """Interior-point kernel family (and, for ``"group"``, lanes per pixel;
+    0 = default width) for libraries of the padded size of N in this process
+    (``linmin_set_kernel``); ``family`` is a name of ``KERNELS`` or its code."""
     fam = KERNELS[family] if isinstance(family, str) else int(family)
-    rc = load().linmin_set_kernel(int(N), int(stage), fam)
+    rc = load().linmin_set_kernel(int(N), int(stage), fam, int(lanes))
     if rc != OK:
         raise LinminError(rc, "linmin_set_kernel")
 
 
 def get_kernel(N: int, stage: int) -> int:
     """Family a library of N uses for ``stage`` now (``linmin_get_kernel``)."""
-    rc = load().linmin_get_kernel(int(N), int(stage))
+    return get_kernel_lanes(N, stage)[0]
+
+
+def get_kernel_lanes(N: int, stage: int) -> tuple:
+    """``(family, lanes)`` a library of N uses for ``stage`` now; lanes is
+    the group width for group kernels, else 0."""
+    ln = ctypes.c_int(0)
+    rc = load().linmin_get_kernel(int(N), int(stage), ctypes.byref(ln))
     if rc < 0:
         raise LinminError(rc, "linmin_get_kernel")
-    return rc
+    return rc, ln.value
 
 
 def default_opts(**kw) -> Opts:

@@ -137,10 +137,21 @@ def test_kernel_choice_without_gpu():
         linmin.set_kernel(36, linmin.STAGE_FP64, "default")
     assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_TILE
     # not compiled for that size or stage; out of range
-    assert lib.linmin_set_kernel(96, linmin.STAGE_FP32, linmin.KERNEL_TILE32) == linmin.EUNSUPPORTED
-    assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_TILE) == linmin.EUNSUPPORTED
-    assert lib.linmin_set_kernel(0, linmin.STAGE_FP64, 0) == linmin.EINVAL
-    assert lib.linmin_set_kernel(129, linmin.STAGE_FP64, 0) == linmin.EINVAL
-    assert lib.linmin_set_kernel(36, 2, 0) == linmin.EINVAL
-    assert lib.linmin_set_kernel(36, linmin.STAGE_FP64, 9) == linmin.EINVAL
-    assert lib.linmin_get_kernel(36, 5) == linmin.EINVAL
+    assert lib.linmin_set_kernel(96, linmin.STAGE_FP32, linmin.KERNEL_TILE32, 0) == linmin.EUNSUPPORTED
+    assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_TILE, 0) == linmin.EUNSUPPORTED
+    assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_GROUP, 3) == linmin.EUNSUPPORTED
+    assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_TILE32, 8) == linmin.EINVAL
+    assert lib.linmin_set_kernel(0, linmin.STAGE_FP64, 0, 0) == linmin.EINVAL
+    assert lib.linmin_set_kernel(129, linmin.STAGE_FP64, 0, 0) == linmin.EINVAL
+    assert lib.linmin_set_kernel(36, 2, 0, 0) == linmin.EINVAL
+    assert lib.linmin_set_kernel(36, linmin.STAGE_FP64, 9, 0) == linmin.EINVAL
+    assert lib.linmin_get_kernel(36, 5, None) == linmin.EINVAL
+    # group widths: the default is the first listed shape, others by choice
+    fam, lanes = linmin.get_kernel_lanes(64, linmin.STAGE_FP32)
+    assert fam == linmin.KERNEL_GROUP and lanes == 16
+    try:
+        linmin.set_kernel(64, linmin.STAGE_FP32, "group", 8)
+        assert linmin.get_kernel_lanes(64, linmin.STAGE_FP32) == (linmin.KERNEL_GROUP, 8)
+    finally:
+        linmin.set_kernel(64, linmin.STAGE_FP32, "default")
+    assert linmin.get_kernel_lanes(64, linmin.STAGE_FP32) == (linmin.KERNEL_GROUP, 16)
