@@ -124,7 +124,25 @@ def test_kernel_choice_without_gpu():
                                                   linmin.KERNEL_GROUP, linmin.KERNEL_TILE32)
     assert (int(defs["LINMIN_STAGE_FP64"]), int(defs["LINMIN_STAGE_FP32"])) == (linmin.STAGE_FP64, linmin.STAGE_FP32)
     lib = linmin.load()
-    # default rule: matrix cores first
+    # the measured table is installed at load: every entry is in force
+    from paper_1402_2518_amd import autotune
+    import json
+    table = json.load(open(linmin.TUNING_PATH))["entries"] if os.path.exists(linmin.TUNING_PATH) else []
+    for e in table:
+        st = linmin.STAGE_FP64 if e["stage"] == "fp64" else linmin.STAGE_FP32
+        assert linmin.get_kernel_lanes(e["N"], st) == (linmin.KERNELS[e["family"]], e["lanes"]), e
+    # the default rule (matrix cores first), with the table's choices cleared
+    for n in range(1, linmin.N_MAX + 1):
+        for st in (linmin.STAGE_FP64, linmin.STAGE_FP32):
+            linmin.set_kernel(n, st, "default")
+    try:
+        _default_rule(lib)
+    finally:
+        if table:
+            assert autotune.install(linmin.TUNING_PATH) == len(table)
+
+
+def _default_rule(lib):
     assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_TILE
     assert linmin.get_kernel(96, linmin.STAGE_FP64) == linmin.KERNEL_ROWCYCLIC
     assert linmin.get_kernel(36, linmin.STAGE_FP32) == linmin.KERNEL_TILE32

@@ -170,15 +170,16 @@ def test_fp32_stage_kernel_families(dev, N):
     S = synth.make_library(w)
     X, s = synth.make_cube(w)
     r = oracle.unmix(S, X, s)
-    assert linmin.get_kernel(N, linmin.STAGE_FP32) == linmin.KERNEL_TILE32
+    before = linmin.get_kernel_lanes(N, linmin.STAGE_FP32)
     try:
         for fam in ("tile32", "group"):
             linmin.set_kernel(N, linmin.STAGE_FP32, fam)
+            assert linmin.get_kernel(N, linmin.STAGE_FP32) == linmin.KERNELS[fam]
             g = _gpu(S, X, s, dev, precision="mixed")
             _compare(g, r, S, X, a_tol=1e-3, f_tol=1e-4)
             _say(f"[gpu]   {fam}: iters {g['iters'].mean():.2f}")
     finally:
-        linmin.set_kernel(N, linmin.STAGE_FP32, "default")
+        linmin.set_kernel(N, linmin.STAGE_FP32, *before)
 
 
 def test_cycling_pixels_converge(dev):
