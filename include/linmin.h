@@ -50,7 +50,13 @@ typedef struct linmin_lib_s *linmin_lib;
 
 /* precision of the interior-point iterations */
 #define LINMIN_FP64 0  /* every step in FP64 */
-#define LINMIN_MIXED 1 /* FP32 Newton steps until mu <= mu_switch, then FP64 */
+#define LINMIN_MIXED 1 /* FP32 Newton steps until mu <= mu_switch, then FP64
+                          steps, finishing step and KKT check; a pixel that
+                          the finishing step does not certify (or whose
+                          steps stop at the cap or lose positive
+                          definiteness) is solved again in FP64 from the
+                          start, so its outputs and iteration count are
+                          those of LINMIN_FP64 */
 
 /* covariance output layouts (per pixel) */
 #define LINMIN_COV_NONE 0   /* out_cov ignored */

@@ -38,6 +38,11 @@ def tile32s():
     return re.findall(r"^LM_TILE32\((\d+)\)", txt, re.M)
 
 
+def cc32s():
+    txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
+    return re.findall(r"^LM_CC32\((\d+),\s*(\d+)\)", txt, re.M)
+
+
 def rc_tiles():
     txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
     return re.findall(r"^LM_RC\((\d+)\)", txt, re.M)
@@ -65,6 +70,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for t in tile32s():
         units.append((os.path.join(CSRC, "ipm_tile32.hip"), os.path.join(BUILD, f"ipm_tile32_{t}.o"),
                       (f"-DLM_TILE32_T={t}",)))
+    for t, q in cc32s():
+        units.append((os.path.join(CSRC, "ipm_cc32.hip"), os.path.join(BUILD, f"ipm_cc32_{t}_{q}.o"),
+                      (f"-DLM_CC32_T={t}", f"-DLM_CC32_Q={q}")))
     for t in rc_tiles():
         units.append((os.path.join(CSRC, "ipm_rc.hip"), os.path.join(BUILD, f"ipm_rc_{t}.o"),
                       (f"-DLM_RC_T={t}",)))

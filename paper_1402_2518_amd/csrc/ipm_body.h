@@ -166,6 +166,10 @@ __device__ __forceinline__ void ipm_pixel(const IpmParams& prm, int64_t p, bool 
   auto el = [&](int m) { return tl.el(m); };
 
   uint32_t flags = 0;
+  // the pass that solves again in FP64 what the mixed form left uncertified
+  // touches only those pixels
+  bool redo = true;
+  if constexpr (MODE == kRetry) redo = inrange && (prm.status[p] & kPxRetry) != 0;
   R bh[C];
   bool nonfin = false;
   static_for<0, C>([&](auto mm) {
@@ -191,7 +195,7 @@ __device__ __forceinline__ void ipm_pixel(const IpmParams& prm, int64_t p, bool 
   const R inv_np = R(1) / R(n + (slo ? 1 : 0));  // complementarity pairs
   R a[C], lam[C], nu = slo ? (R)prm.lambda0 : R(0), s = slo ? inv_np : R(0);
   int it = 0;
-  bool start = inrange && !nonfin;
+  bool start = inrange && !nonfin && redo;
   if constexpr (MODE == kStage2) {
     if (inrange) {
       const uint8_t f = prm.st_flag[p];
@@ -521,7 +525,8 @@ __device__ __forceinline__ void ipm_pixel(const IpmParams& prm, int64_t p, bool 
     if (inrange && prm.sigma) sgm = (double)prm.sigma[p];
     if (!(sgm > 0.0) || !fin(sgm)) flags |= kPxBadSigma;
     const double qnan = __builtin_nan("");
-    if (inrange) {
+    const bool wout = inrange && redo;
+    if (wout) {
       static_for<0, C>([&](auto mm) {
         constexpr int m = decltype(mm)::value;
         if (vm[m]) {
@@ -555,13 +560,13 @@ __device__ __forceinline__ void ipm_pixel(const IpmParams& prm, int64_t p, bool 
       });
       ba = TL::sum(ba);
       aga = TL::sum(aga);
-      if (inrange && tl.writer()) {
+      if (wout && tl.writer()) {
         double F = (prm.c[p] - 2.0 * prm.gamma * ba + prm.gamma * aga) / (sgm * sgm);
         if (nonfin || (flags & kPxBadSigma)) F = qnan;
         prm.objective[p] = F;
       }
     }
-    if (inrange && tl.writer()) {
+    if (wout && tl.writer()) {
       if (prm.status) prm.status[p] = (uint8_t)flags;
       if (prm.iters) prm.iters[p] = it;
     }

@@ -4,8 +4,10 @@
 //   row-cyclic  FP64, one pixel per wavefront on the 4x4x4 FP64 matrix cores
 //   tile        FP64, four pixels per wavefront on the 4x4x4 FP64 matrix cores
 //   group       FP64 or FP32, a group of lanes per pixel on the vector units
-//   tile32      FP32 (first stage of the mixed form), sixteen pixels per
-//               wavefront on the 4x4x1 FP32 matrix cores
+//   tile32      FP32 (first stage of the mixed form) on the 4x4x1 FP32
+//               matrix cores: sixteen pixels per wavefront, or for the
+//               larger libraries a pixel's tile columns dealt out over Q
+//               blocks (16 / Q pixels per wavefront)
 // The default choice per padded size NC is the first family compiled for it
 // in the order above (FP32: tile32, then group), a group kernel with the
 // first width listed for NC.  A measured table installed with
@@ -26,11 +28,46 @@ namespace lm {
 #define LM_TILE(t) int ipm_tile_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_RC(t) int ipm_rc_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_TILE32(t) int ipm_tile32_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
+#define LM_CC32(t, q) \
+  int ipm_cc32_entry_##t##_##q(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
 #undef LM_TILE32
+#undef LM_CC32
+
+// quads per pixel of the FP32 column-cyclic shape for nc, or 0
+static int cc32_quads(int nc) {
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t)
+#define LM_RC(t)
+#define LM_TILE32(t)
+#define LM_CC32(t, q) \
+  if (4 * t == nc) return q;
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+#undef LM_RC
+#undef LM_TILE32
+#undef LM_CC32
+  return 0;
+}
+
+// an FP32 tile shape (sixteen pixels per wavefront) exists for nc
+static bool tile32_has(int nc) {
+  bool have = false;
+#define LM_SHAPE(t, nc_, g)
+#define LM_TILE(t)
+#define LM_RC(t)
+#define LM_TILE32(t) have |= (4 * t == nc);
+#include "ipm_shapes.def"
+#undef LM_SHAPE
+#undef LM_TILE
+#undef LM_RC
+#undef LM_TILE32
+  return have;
+}
 
 int ipm_shape_nc(int n) {
   int best = -1;
@@ -113,16 +150,7 @@ bool ipm_family_available(int nc, bool fp32, int fam) {
       return have;
     case kFamTile32:
       if (!fp32 || nc % 4) return false;
-#define LM_SHAPE(t, nc_, g)
-#define LM_TILE(t)
-#define LM_RC(t)
-#define LM_TILE32(t) have |= (4 * t == nc);
-#include "ipm_shapes.def"
-#undef LM_SHAPE
-#undef LM_TILE
-#undef LM_RC
-#undef LM_TILE32
-      return have;
+      return tile32_has(nc) || cc32_quads(nc) > 0;
     case kFamGroup:
       return group_lanes(nc, fp32) > 0;
   }
@@ -203,11 +231,12 @@ int ipm_kernel_class_of(int n, bool fp32, bool stable, int code) {
   return -1;
 }
 
-int ipm_pixels_per_block_code(int code) {
+int ipm_pixels_per_block_code(int code, int nc) {
   switch (code & 0xff) {
     case kFamRowCyclic: return 4;   // one pixel per wavefront, four wavefronts
     case kFamTile: return 16;       // four pixels per wavefront, four wavefronts
-    case kFamTile32: return 64;     // sixteen pixels per wavefront, four wavefronts
+    case kFamTile32:                // sixteen pixels per wavefront, or 16 / Q (column-cyclic), four wavefronts
+      return tile32_has(nc) ? 64 : (cc32_quads(nc) > 0 ? 4 * (16 / cc32_quads(nc)) : -1);
     case kFamGroup: return (code >> 8) > 0 ? 4 * (64 / (code >> 8)) : -1;
   }
   return -1;
@@ -215,7 +244,7 @@ int ipm_pixels_per_block_code(int code) {
 
 int ipm_pixels_per_block(int n, bool fp32) {
   const int code = ipm_choice_code(n, fp32);
-  return code < 0 ? -1 : ipm_pixels_per_block_code(code);
+  return code < 0 ? -1 : ipm_pixels_per_block_code(code, ipm_shape_nc(n));
 }
 
 // launch the kernel that code (family | group width << 8) names
@@ -253,11 +282,14 @@ static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool
 #define LM_RC(t)
 #define LM_TILE32(t) \
       if (4 * t == nc) return ipm_tile32_entry_##t(p, b, mode, st);
+#define LM_CC32(t, q) \
+      if (4 * t == nc) return ipm_cc32_entry_##t##_##q(p, b, mode, st);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
 #undef LM_TILE
 #undef LM_RC
 #undef LM_TILE32
+#undef LM_CC32
       break;
     case kFamGroup: {
       const int lanes = code >> 8;
@@ -280,6 +312,19 @@ static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool
 int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st) {
   if (p.P <= 0) return 0;
   return dispatch(p.n, p, nullptr, mode, fp32, ipm_choice_code(p.n, fp32), st);
+}
+
+int ipm_retry_code(int n) {
+  const int nc = ipm_shape_nc(n);
+  if (nc < 0) return -1;
+  if (ipm_family_available(nc, false, kFamTile)) return kFamTile;
+  if (ipm_family_available(nc, false, kFamRowCyclic)) return kFamRowCyclic;
+  return -1;
+}
+
+int launch_ipm_retry(const IpmParams& p, hipStream_t st) {
+  if (p.P <= 0) return 0;
+  return dispatch(p.n, p, nullptr, kRetry, false, ipm_retry_code(p.n), st);
 }
 
 int launch_ipm_batch(int n, int constraint, int stable, const IpmBatch& b, int mode, bool fp32, int code,

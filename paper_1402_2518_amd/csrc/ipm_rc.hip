@@ -275,12 +275,16 @@ __device__ __forceinline__ void ipm_rc_body(const IpmParams& prm, int64_t wg) {
   __shared__ double sG[NP * NP];
   __shared__ double sx[WPB * 16];
   __shared__ double sw[WPB * TL::R * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = wg * WPB + wave;
+  if constexpr (MODE == kRetry) {
+    // most workgroups hold no pixel to solve again
+    if (!__syncthreads_or(p < prm.P && (prm.status[p] & kPxRetry) != 0)) return;
+  }
   const double* Gsrc = static_cast<const double*>(prm.Gh);
   for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) sG[i] = Gsrc[i];
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t p = wg * WPB + wave;
   TL tl;
   tl.x = lane >> 4;
   tl.b = (lane >> 2) & 3;
@@ -332,6 +336,8 @@ static int launch_rc_c(const IpmParams& p, const IpmBatch* b, int mode, hipStrea
     launch_rc_m<T, kFull, CONS>(p, b, st);
   else if (mode == kStage2)
     launch_rc_m<T, kStage2, CONS>(p, b, st);
+  else if (mode == kRetry)
+    launch_rc_m<T, kRetry, CONS>(p, b, st);
   else
     return -5;
   return hipGetLastError() == hipSuccess ? 0 : -3;

@@ -324,14 +324,17 @@ __device__ __forceinline__ void ipm_tile_body(const IpmParams& prm, int64_t wg) 
   constexpr int NP = TL::NP;
   __shared__ double sG[NP * NP];
   __shared__ double sx[16 * 18];
-  const double* Gsrc = static_cast<const double*>(prm.Gh);
-  for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) sG[i] = Gsrc[i];
-  __syncthreads();
-
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int blk = (lane >> 2) & 3, x = lane >> 4, z = lane & 3;
   const int pib = wave * 4 + blk;
   const int64_t p = wg * 16 + pib;
+  if constexpr (MODE == kRetry) {
+    // most workgroups hold no pixel to solve again
+    if (!__syncthreads_or(p < prm.P && (prm.status[p] & kPxRetry) != 0)) return;
+  }
+  const double* Gsrc = static_cast<const double*>(prm.Gh);
+  for (int i = threadIdx.x; i < NP * NP; i += blockDim.x) sG[i] = Gsrc[i];
+  __syncthreads();
 
   TL tl;
   tl.x = x;
@@ -378,6 +381,8 @@ static int launch_tile_c(const IpmParams& p, const IpmBatch* b, int mode, hipStr
     launch_tile_m<T, kFull, CONS, ST>(p, b, st);
   else if (mode == kStage2)
     launch_tile_m<T, kStage2, CONS, ST>(p, b, st);
+  else if (mode == kRetry)
+    launch_tile_m<T, kRetry, CONS, ST>(p, b, st);
   else
     return -5;
   return hipGetLastError() == hipSuccess ? 0 : -3;

@@ -11,6 +11,10 @@ enum IpmMode : int {
   kFull = 0,    // start -> iterate to tolerance -> finishing step -> outputs
   kStage1 = 1,  // start -> iterate until mu <= mu_switch -> save state
   kStage2 = 2,  // load state -> iterate to tolerance -> finishing step -> outputs
+  kRetry = 3,   // mixed form, after stage 2: pixels whose status says the
+                // finishing step did not certify (or the iterations stopped
+                // early) are solved again in FP64 from the start; the others
+                // are left as they are
 };
 
 // Per-pixel status bits (same meaning as LINMIN_PX_* in linmin.h).
@@ -88,10 +92,14 @@ int ipm_set_family(int nc, bool fp32, int fam, int lanes);  // fam 0 = default r
 int ipm_shape_nc(int n);                      // padded size NC used for a library of size n
 int ipm_choice_code(int n, bool fp32);        // kernel used now: family | group width << 8
 int ipm_pixels_per_block(int n, bool fp32);   // pixels of one workgroup for that kernel
-int ipm_pixels_per_block_code(int code);
+int ipm_pixels_per_block_code(int code, int nc);  // for kernel code at padded size nc
 int ipm_kernel_class(int n, bool fp32, bool stable);  // launches of equal class can share a batch
 int ipm_kernel_class_of(int n, bool fp32, bool stable, int code);  // the same for kernel code
 int launch_ipm(const IpmParams& p, int mode, bool fp32, hipStream_t st);
+// the kRetry pass of the mixed form on the FP64 matrix-core kernel for p.n
+int launch_ipm_retry(const IpmParams& p, hipStream_t st);
+int ipm_retry_code(int n);                    // its kernel code
+constexpr uint32_t kPxRetry = kPxInexact | kPxMaxit | kPxNotPd;  // status bits that send a pixel to kRetry
 // batched: every job of b has a library with ipm_kernel_class(n, fp32,
 // stable) equal to that of n, planned for the kernel code names (fixed when
 // the batch was planned); constraint and stable as in IpmParams

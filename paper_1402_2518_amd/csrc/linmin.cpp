@@ -234,6 +234,9 @@ int unmix_ws(linmin_lib lib, const float* cube, int64_t P, const float* sigma, d
         prm.Gh = lib->Gh64;
         rc = from_launch(launch_ipm(prm, kStage2, false, st));
       }
+      // what the finishing step could not certify after the hand-over is
+      // solved again in FP64 from the start
+      if (rc == LINMIN_OK) rc = from_launch(launch_ipm_retry(prm, st));
     } else {
       prm.Gh = lib->Gh64;
       rc = from_launch(launch_ipm(prm, kFull, false, st));
@@ -588,8 +591,8 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   // job tables
   std::map<int, Group<lm::ProjJob>> proj;  // by column blocks
   Group<lm::ProjJob> quad;
-  std::map<int, Group<lm::IpmParams>> ipm1, ipm2;  // by kernel class: FP64 (or stage 2), FP32 stage 1
-  std::map<int, std::pair<int, int>> class_n1, class_n2;  // a library size of each class, its kernel code
+  std::map<int, Group<lm::IpmParams>> ipm1, ipm2, ipm3;  // by kernel class: FP64 (or stage 2), FP32 stage 1, retry
+  std::map<int, std::pair<int, int>> class_n1, class_n2, class_n3;  // a library size of each class, its kernel code
   std::map<int, int> code1, code2;                         // kernel code per library size
   Group<lm::CovJob> cov[3];
   int qcap = 0;
@@ -615,14 +618,19 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
     const int c2 = code2.count(lib->N) ? code2[lib->N] : (code2[lib->N] = lm::ipm_choice_code(lib->N, false));
     const int k2 = lm::ipm_kernel_class_of(lib->N, false, lib->stable != 0, c2);
     prm.Gh = lib->Gh64;
-    ipm2[k2].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c2)));
+    ipm2[k2].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c2, lib->NC)));
     class_n2[k2] = {lib->N, c2};
     if (mixed) {
       const int c1 = code1.count(lib->N) ? code1[lib->N] : (code1[lib->N] = lm::ipm_choice_code(lib->N, true));
       const int k1 = lm::ipm_kernel_class_of(lib->N, true, lib->stable != 0, c1);
       prm.Gh = lib->Gh32;
-      ipm1[k1].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c1)));
+      ipm1[k1].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c1, lib->NC)));
       class_n1[k1] = {lib->N, c1};
+      const int c3 = lm::ipm_retry_code(lib->N);
+      const int k3 = lm::ipm_kernel_class_of(lib->N, false, lib->stable != 0, c3);
+      prm.Gh = lib->Gh64;
+      ipm3[k3].add(prm, cdiv(P, lm::ipm_pixels_per_block_code(c3, lib->NC)));
+      class_n3[k3] = {lib->N, c3};
     }
     if (want_cov) {
       const lm::CovJob cj{lib->N, P, lib->Gh64, lib->NC, (double*)at(w.dcov), (double*)at(w.dcorner), J.sigma,
@@ -640,6 +648,7 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   quad.place(im);
   for (auto& kv : ipm1) kv.second.place(im);
   for (auto& kv : ipm2) kv.second.place(im);
+  for (auto& kv : ipm3) kv.second.place(im);
   for (auto& g : cov) g.place(im);
   b->tab_bytes = im.bytes.size();
   if (b->tab_bytes) {
@@ -674,6 +683,7 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
   if (mixed) {
     add_ipm(ipm1, class_n1, lm::kStage1, true);
     add_ipm(ipm2, class_n2, lm::kStage2, false);
+    add_ipm(ipm3, class_n3, lm::kRetry, false);
   } else {
     add_ipm(ipm2, class_n2, lm::kFull, false);
   }
@@ -691,7 +701,11 @@ int linmin_batch_create(const linmin_job* jobs, int n_jobs, const linmin_opts* o
     std::map<int, double> cost;  // by padded size
     for (const auto& g : b->ipm) {
       const double nc = lm::ipm_shape_nc(g.n);
-      const double pixels = (double)g.b.blocks * lm::ipm_pixels_per_block_code(g.code);
+      if (g.mode == lm::kRetry) {  // few pixels do any work
+        cost[(int)nc] += 0.0;
+        continue;
+      }
+      const double pixels = (double)g.b.blocks * lm::ipm_pixels_per_block_code(g.code, (int)nc);
       cost[(int)nc] += pixels * nc * nc * nc;
     }
     std::vector<std::pair<double, int>> order;

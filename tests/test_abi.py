@@ -146,7 +146,8 @@ def _default_rule(lib):
     assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_TILE
     assert linmin.get_kernel(96, linmin.STAGE_FP64) == linmin.KERNEL_ROWCYCLIC
     assert linmin.get_kernel(36, linmin.STAGE_FP32) == linmin.KERNEL_TILE32
-    assert linmin.get_kernel(64, linmin.STAGE_FP32) == linmin.KERNEL_GROUP
+    assert linmin.get_kernel(64, linmin.STAGE_FP32) == linmin.KERNEL_TILE32  # column-cyclic FP32 tiles
+    assert linmin.get_kernel(8, linmin.STAGE_FP32) == linmin.KERNEL_TILE32
     try:
         linmin.set_kernel(33, linmin.STAGE_FP64, "group")  # same padded size as 36
         assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_GROUP
@@ -155,7 +156,7 @@ def _default_rule(lib):
         linmin.set_kernel(36, linmin.STAGE_FP64, "default")
     assert linmin.get_kernel(36, linmin.STAGE_FP64) == linmin.KERNEL_TILE
     # not compiled for that size or stage; out of range
-    assert lib.linmin_set_kernel(96, linmin.STAGE_FP32, linmin.KERNEL_TILE32, 0) == linmin.EUNSUPPORTED
+    assert lib.linmin_set_kernel(96, linmin.STAGE_FP64, linmin.KERNEL_TILE, 0) == linmin.EUNSUPPORTED
     assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_TILE, 0) == linmin.EUNSUPPORTED
     assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_GROUP, 3) == linmin.EUNSUPPORTED
     assert lib.linmin_set_kernel(36, linmin.STAGE_FP32, linmin.KERNEL_TILE32, 8) == linmin.EINVAL
@@ -165,11 +166,11 @@ def _default_rule(lib):
     assert lib.linmin_set_kernel(36, linmin.STAGE_FP64, 9, 0) == linmin.EINVAL
     assert lib.linmin_get_kernel(36, 5, None) == linmin.EINVAL
     # group widths: the default is the first listed shape, others by choice
-    fam, lanes = linmin.get_kernel_lanes(64, linmin.STAGE_FP32)
-    assert fam == linmin.KERNEL_GROUP and lanes == 16
     try:
+        linmin.set_kernel(64, linmin.STAGE_FP32, "group")
+        assert linmin.get_kernel_lanes(64, linmin.STAGE_FP32) == (linmin.KERNEL_GROUP, 16)
         linmin.set_kernel(64, linmin.STAGE_FP32, "group", 8)
         assert linmin.get_kernel_lanes(64, linmin.STAGE_FP32) == (linmin.KERNEL_GROUP, 8)
     finally:
         linmin.set_kernel(64, linmin.STAGE_FP32, "default")
-    assert linmin.get_kernel_lanes(64, linmin.STAGE_FP32) == (linmin.KERNEL_GROUP, 16)
+    assert linmin.get_kernel_lanes(64, linmin.STAGE_FP32) == (linmin.KERNEL_TILE32, 0)

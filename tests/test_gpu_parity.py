@@ -159,14 +159,15 @@ def test_library_sizes(dev, N):
                  f_tol=1e-9 if precision == "fp64" else 1e-4)
 
 
-@pytest.mark.parametrize("N", [8, 21, 36])
+@pytest.mark.parametrize("N", [8, 21, 36, 45, 64, 90, 128])
 def test_fp32_stage_kernel_families(dev, N):
     """The mixed form's FP32 stage on each kernel family compiled for the
-    size (the 4x4x1 matrix-core tiles and the lane groups): both hand an
+    size (the 4x4x1 matrix-core tiles, sixteen pixels per wavefront up to
+    N = 36 and column-cyclic above, and the lane groups): both hand an
     iterate to the same FP64 stage, so both must meet the oracle."""
     from paper_1402_2518_amd import linmin
     _say(f"[gpu] FP32 stage kernel families N={N}")
-    w = synth.custom_workload(N, 96, 1203, seed=700 + N, n_extra=4, k_max=4)
+    w = synth.custom_workload(N, max(96, N + 8), 1203 if N <= 64 else 397, seed=700 + N, n_extra=4, k_max=4)
     S = synth.make_library(w)
     X, s = synth.make_cube(w)
     r = oracle.unmix(S, X, s)
