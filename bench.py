@@ -28,8 +28,8 @@ PEAK_FP64 = 78.6e12          # MI355X FP64, dense matrix cores and vector units 
 PEAK_HBM = 8.0e12            # bytes/s
 PROFILE = os.path.join(ROOT, "profiles", "orbital_N36_L240_kernels.md")
 IPM_KERNEL = "lm::ipm_tile_kernel<9, 0, 0, false>"
-IPM_SOURCES = ("paper_1402_2518_amd/csrc/ipm_tile.hip", "paper_1402_2518_amd/csrc/common.h",
-               "paper_1402_2518_amd/csrc/kernels.h")
+IPM_SOURCES = ("paper_1402_2518_amd/csrc/ipm_tile.hip", "paper_1402_2518_amd/csrc/ipm_body.h",
+               "paper_1402_2518_amd/csrc/common.h", "paper_1402_2518_amd/csrc/kernels.h")
 
 
 def profiled_traffic():
@@ -126,6 +126,13 @@ def workload_leg(name, args, dev, stream, steps, warmup, latency_calls, variants
                     "kernel": kname + " (FP64, 4x4x4 matrix-core tiles)", "kernel_ms": ipm_ms,
                     "flops_per_launch": flops, "mean_iters": float(it.mean()),
                     "flops_per_iteration": ipm_flops_per_iteration(N)}
+        fam = {v: k for k, v in linmin.KERNELS.items()}
+        stages = [("fp64", linmin.STAGE_FP64)] if prec == "fp64" else [("fp32", linmin.STAGE_FP32),
+                                                                         ("fp64", linmin.STAGE_FP64)]
+        res[prec]["kernels"] = {}
+        for sname, stg in stages:
+            f_, l_ = linmin.get_kernel_lanes(N, stg)
+            res[prec]["kernels"][sname] = fam[f_] + (f"/{l_}" if l_ else "")
         print(f"# {name} {prec}: {wall / steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
         if latency_calls > 0:
             _, stl = run(prec, latency_calls, 1, buf)
