@@ -45,7 +45,7 @@ def cc32s():
 
 def rc_tiles():
     txt = open(os.path.join(CSRC, "ipm_shapes.def")).read()
-    return re.findall(r"^LM_RC\((\d+)\)", txt, re.M)
+    return re.findall(r"^LM_RC\((\d+),\s*(\d+)\)", txt, re.M)
 
 
 def _compile(src, obj, extra=()):
@@ -73,9 +73,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for t, q in cc32s():
         units.append((os.path.join(CSRC, "ipm_cc32.hip"), os.path.join(BUILD, f"ipm_cc32_{t}_{q}.o"),
                       (f"-DLM_CC32_T={t}", f"-DLM_CC32_Q={q}")))
-    for t in rc_tiles():
-        units.append((os.path.join(CSRC, "ipm_rc.hip"), os.path.join(BUILD, f"ipm_rc_{t}.o"),
-                      (f"-DLM_RC_T={t}",)))
+    for t, bb in rc_tiles():
+        units.append((os.path.join(CSRC, "ipm_rc.hip"), os.path.join(BUILD, f"ipm_rc_{t}_{bb}.o"),
+                      (f"-DLM_RC_T={t}", f"-DLM_RC_B={bb}")))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_compile, s, o, e) for s, o, e in units]

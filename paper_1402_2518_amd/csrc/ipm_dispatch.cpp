@@ -26,7 +26,7 @@ namespace lm {
 #define LM_SHAPE(t, nc, g) \
   int ipm_entry_##t##_##nc##_##g(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_TILE(t) int ipm_tile_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
-#define LM_RC(t) int ipm_rc_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
+#define LM_RC(t, bb) int ipm_rc_entry_##t##_##bb(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_TILE32(t) int ipm_tile32_entry_##t(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
 #define LM_CC32(t, q) \
   int ipm_cc32_entry_##t##_##q(const IpmParams& p, const IpmBatch* b, int mode, hipStream_t st);
@@ -41,7 +41,7 @@ namespace lm {
 static int cc32_quads(int nc) {
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #define LM_CC32(t, q) \
   if (4 * t == nc) return q;
@@ -59,7 +59,7 @@ static bool tile32_has(int nc) {
   bool have = false;
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t) have |= (4 * t == nc);
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -74,7 +74,7 @@ int ipm_shape_nc(int n) {
 #define LM_SHAPE(t, nc, g) \
   if (nc >= n && (best < 0 || nc < best)) best = nc;
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -90,7 +90,7 @@ static int group_lanes(int nc, bool fp32) {
 #define LM_SHAPE(t, nc_, g) \
   if (nc_ == nc && (fp32 == (sizeof(t) == 4))) return g;
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -105,7 +105,7 @@ static bool group_has(int nc, bool fp32, int g) {
 #define LM_SHAPE(t, nc_, g_) \
   if (nc_ == nc && (fp32 == (sizeof(t) == 4)) && g_ == g) return true;
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -128,7 +128,7 @@ bool ipm_family_available(int nc, bool fp32, int fam) {
       if (fp32 || nc % 16) return false;
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
-#define LM_RC(t) have |= (4 * t == nc);
+#define LM_RC(t, bb) have |= (4 * t == nc);
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -140,7 +140,7 @@ bool ipm_family_available(int nc, bool fp32, int fam) {
       if (fp32 || nc % 4) return false;
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t) have |= (4 * t == nc);
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -255,8 +255,8 @@ static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool
     case kFamRowCyclic:
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
-#define LM_RC(t) \
-      if (4 * t == nc) return ipm_rc_entry_##t(p, b, mode, st);
+#define LM_RC(t, bb) \
+      if (4 * t == nc) return ipm_rc_entry_##t##_##bb(p, b, mode, st);
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -268,7 +268,7 @@ static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t) \
       if (4 * t == nc) return ipm_tile_entry_##t(p, b, mode, st);
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE
@@ -279,7 +279,7 @@ static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool
     case kFamTile32:
 #define LM_SHAPE(t, nc_, g)
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t) \
       if (4 * t == nc) return ipm_tile32_entry_##t(p, b, mode, st);
 #define LM_CC32(t, q) \
@@ -296,7 +296,7 @@ static int dispatch(int n, const IpmParams& p, const IpmBatch* b, int mode, bool
 #define LM_SHAPE(t, nc_, g) \
       if (nc_ == nc && (fp32 == (sizeof(t) == 4)) && g == lanes) return ipm_entry_##t##_##nc_##_##g(p, b, mode, st);
 #define LM_TILE(t)
-#define LM_RC(t)
+#define LM_RC(t, bb)
 #define LM_TILE32(t)
 #include "ipm_shapes.def"
 #undef LM_SHAPE

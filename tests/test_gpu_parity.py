@@ -183,6 +183,31 @@ def test_fp32_stage_kernel_families(dev, N):
         linmin.set_kernel(N, linmin.STAGE_FP32, *before)
 
 
+@pytest.mark.parametrize("N", [50, 64])
+def test_fp64_kernel_families(dev, N):
+    """The FP64 path on each matrix-core layout compiled for the size (the
+    four-pixel tiles and the row-cyclic tiles of a pixel over two blocks), in
+    both precisions (the FP64 kernel is also the mixed form's second stage
+    and its retry): each must meet the oracle."""
+    from paper_1402_2518_amd import linmin
+    _say(f"[gpu] FP64 kernel families N={N}")
+    w = synth.custom_workload(N, 2 * N, 611, seed=900 + N, n_extra=4, k_max=4)
+    S = synth.make_library(w)
+    X, s = synth.make_cube(w)
+    r = oracle.unmix(S, X, s)
+    before = linmin.get_kernel_lanes(N, linmin.STAGE_FP64)
+    try:
+        for fam in ("rowcyclic", "tile"):
+            linmin.set_kernel(N, linmin.STAGE_FP64, fam)
+            for precision in ("fp64", "mixed"):
+                g = _gpu(S, X, s, dev, precision=precision)
+                _compare(g, r, S, X, a_tol=1e-6 if precision == "fp64" else 1e-3,
+                         f_tol=1e-9 if precision == "fp64" else 1e-4)
+                _say(f"[gpu]   {fam} {precision}: iters {g['iters'].mean():.2f}")
+    finally:
+        linmin.set_kernel(N, linmin.STAGE_FP64, *before)
+
+
 def test_cycling_pixels_converge(dev):
     _say("[gpu] orbital pixels that make plain Mehrotra cycle")
     from test_oracle import cycling_pixels
