@@ -261,10 +261,12 @@ def batch_leg(args, dev, stream):
     return out
 
 
-def serve_leg(args, dev, rate=None, seconds=None):
+def serve_leg(args, dev, rate=None, seconds=None, host_inputs=False):
     """Poisson arrivals of cubes of 8 resident libraries through the request
     loop: latency under load, and sampled requests checked against the same
-    request served alone and against the oracle."""
+    request served alone and against the oracle.  host_inputs: the arriving
+    cubes sit in pinned host memory and each request includes its
+    host-to-device copy."""
     import torch
     import oracle
     from paper_1402_2518_amd import linmin, serve, synth
@@ -280,6 +282,8 @@ def serve_leg(args, dev, rate=None, seconds=None):
         pools[k] = synth.make_cube_device(w, S, dev)
         host[k] = S
         libs[k].unmix(pools[k][0][:64], pools[k][1][:64], cov="full")  # loads the kernels
+        if host_inputs:
+            pools[k] = tuple(t.cpu().pin_memory() for t in pools[k])
     torch.cuda.synchronize()
     rate = args.serve_rate if rate is None else rate
     seconds = args.serve_seconds if seconds is None else seconds
@@ -303,12 +307,14 @@ def serve_leg(args, dev, rate=None, seconds=None):
                 "precision": "fp64", "slots": srv.slots, "streams": len(srv.streams),
                 "hbm_budget_bytes": srv.budget, "max_running": srv.stats["max_running"],
                 "max_bytes_in_use": srv.stats["max_bytes"],
-                "inputs": "device-resident cube pools (200,000 pixels per library), requests are row ranges"})
+                "inputs": ("pinned host cube pools (200,000 pixels per library), requests are row ranges copied to "
+                           "the device on a copy stream inside each request's latency") if host_inputs else
+                          "device-resident cube pools (200,000 pixels per library), requests are row ranges"})
     same, err = True, 0.0
     for r in done:
         if not r.keep:
             continue
-        alone = libs[r.lib].unmix(r.cube, r.sigma, precision="fp64", cov="full")
+        alone = libs[r.lib].unmix(r.cube.to(dev), r.sigma.to(dev), precision="fp64", cov="full")
         torch.cuda.synchronize()
         same &= all(torch.equal(r.out[k].nan_to_num(3.5), alone[k].nan_to_num(3.5)) for k in ("a", "cov", "status"))
         X8 = r.cube[:4].cpu().numpy()
@@ -350,6 +356,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0, help="cubes per second arriving")
     ap.add_argument("--serve-light-rate", type=float, default=25.0,
                     help="a second, lighter stream (20 s) to show latency below saturation (0 = skip)")
+    ap.add_argument("--serve-host-seconds", type=float, default=20.0,
+                    help="a third stream at the configured rate whose cubes arrive in host memory (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -421,6 +429,9 @@ def main():
         if args.serve_light_rate > 0:
             torch.cuda.empty_cache()
             result["serving_light"] = serve_leg(args, dev, rate=args.serve_light_rate, seconds=20.0)
+        if args.serve_host_seconds > 0:
+            torch.cuda.empty_cache()
+            result["serving_host_inputs"] = serve_leg(args, dev, seconds=args.serve_host_seconds, host_inputs=True)
 
     if not args.no_cpu:
         S, X, s, a64h = host

@@ -15,6 +15,10 @@ start while earlier ones are still running.  Every pixel is
 solved independently, so a request's result does not depend on what else was
 running.
 
+A request's cube may also arrive in (pinned) host memory: it is then copied
+to the device on a copy stream of its own, and the unmix call waits for that
+copy only, so transfers of arriving cubes overlap the solves of earlier ones.
+
 Host-side scheduling only: the arithmetic is in the library's kernels.
 """
 from __future__ import annotations
@@ -35,8 +39,8 @@ _COV_PER = {None: lambda n: 0, "none": lambda n: 0, "full": lambda n: n * n,
 class Request:
     rid: int
     lib: str             # key of a resident library
-    cube: object         # P x L float32 device tensor
-    sigma: object        # P float32 device tensor or None
+    cube: object         # P x L float32 tensor, on the device or in pinned host memory
+    sigma: object        # P float32 tensor (same place as cube) or None
     arrival: float       # seconds from the start of the run
     keep: bool = True    # keep the outputs after completion
     # filled by the server
@@ -44,14 +48,16 @@ class Request:
     t_done: float = float("nan")
     footprint: int = 0
     out: dict | None = None
+    cube_dev: object = None  # device copy of a host cube while the request runs
 
 
-def footprint(lib: linmin.Library, P: int, precision: str, cov: str | None) -> int:
-    """Device bytes a request holds while it runs: its outputs and the
-    workspace of the call."""
+def footprint(lib: linmin.Library, P: int, precision: str, cov: str | None, host_input: bool = False) -> int:
+    """Device bytes a request holds while it runs: its outputs, the
+    workspace of the call and, for a cube in host memory, its device copy."""
     n = lib.N
     outs = P * (8 * n + 8 * _COV_PER[cov](n) + 1 + 4 + 8)
-    return outs + lib.workspace_bytes(P, precision, cov)
+    inputs = P * (4 * lib.L + 4) if host_input else 0
+    return outs + inputs + lib.workspace_bytes(P, precision, cov)
 
 
 def admissible(head_bytes: int, used_bytes: int, budget: int, running: int, slots: int) -> bool:
@@ -85,6 +91,7 @@ class Server:
         self.libs = libraries
         self.max_pass_s = float(max_pass_s)
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.copy_stream = torch.cuda.Stream()  # host-to-device copies of arriving cubes
         self.slots = slots
         self.budget = int(hbm_budget)
         self.precision = precision
@@ -96,15 +103,28 @@ class Server:
         lib = self.libs[r.lib]
         P, n = r.cube.shape[0], lib.N
         st = self.streams[k % len(self.streams)]
-        # the cube (and sigma) may still be in production on the caller's
-        # stream: order this request after it, and tell the caching allocator
-        # that the side stream uses them
-        st.wait_stream(torch.cuda.current_stream(r.cube.device))
-        r.cube.record_stream(st)
-        if r.sigma is not None:
-            r.sigma.record_stream(st)
+        dev = torch.device("cuda", torch.cuda.current_device()) if r.cube.device.type == "cpu" else r.cube.device
+        if r.cube.device.type == "cpu":
+            # copy the arriving cube on the copy stream; the solve waits for it
+            cs = self.copy_stream
+            with torch.cuda.stream(cs):
+                cube = r.cube.to(dev, non_blocking=True)
+                sigma = None if r.sigma is None else r.sigma.to(dev, non_blocking=True)
+            st.wait_stream(cs)
+            cube.record_stream(st)
+            if sigma is not None:
+                sigma.record_stream(st)
+            r.cube_dev = (cube, sigma)  # held until the request completes
+        else:
+            # the cube (and sigma) may still be in production on the caller's
+            # stream: order this request after it, and tell the caching
+            # allocator that the side stream uses them
+            cube, sigma = r.cube, r.sigma
+            st.wait_stream(torch.cuda.current_stream(dev))
+            cube.record_stream(st)
+            if sigma is not None:
+                sigma.record_stream(st)
         with torch.cuda.stream(st):
-            dev = r.cube.device
             shp = {None: None, "none": None, "full": (P, n, n), "packed": (P, n * (n + 1) // 2),
                    "diag": (P, n)}[self.cov]
             out = {"a": torch.empty((P, n), dtype=torch.float64, device=dev),
@@ -112,7 +132,7 @@ class Server:
                    "status": torch.empty(P, dtype=torch.uint8, device=dev),
                    "iters": torch.empty(P, dtype=torch.int32, device=dev),
                    "objective": torch.empty(P, dtype=torch.float64, device=dev)}
-            lib.unmix_into(r.cube, r.sigma, out["a"], out["cov"], out["status"], out["iters"], out["objective"],
+            lib.unmix_into(cube, sigma, out["a"], out["cov"], out["status"], out["iters"], out["objective"],
                            precision=self.precision, cov=self.cov, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
@@ -128,7 +148,8 @@ class Server:
         used = 0
         k = 0
         for r in pending:
-            r.footprint = footprint(self.libs[r.lib], r.cube.shape[0], self.precision, self.cov)
+            r.footprint = footprint(self.libs[r.lib], r.cube.shape[0], self.precision, self.cov,
+                                    host_input=r.cube.device.type == "cpu")
         t0 = time.perf_counter()
         while pending or waiting or running:
             now = time.perf_counter() - t0
@@ -141,6 +162,7 @@ class Server:
                     r.t_done = time.perf_counter() - t0
                     used -= r.footprint
                     running.remove(item)
+                    r.cube_dev = None
                     if not r.keep:
                         r.out = None
                     done.append(r)

@@ -593,8 +593,9 @@ def test_dependent_spectra_first(dev, constraint):
 def test_serving_mix_identical_alone(dev):
     """Requests of four resident libraries (N = 8..96) arriving within 50 ms
     run concurrently under an HBM budget that admits only some at a time;
-    each result equals the same request served alone, bit for bit, and
-    sampled pixels match the oracle."""
+    every third cube arrives in pinned host memory and is copied in by the
+    server; each result equals the same request served alone, bit for bit,
+    and sampled pixels match the oracle."""
     from paper_1402_2518_amd import linmin, serve
     _say("[gpu] serving loop: 24 overlapping requests")
     rng = np.random.default_rng(77)
@@ -605,17 +606,21 @@ def test_serving_mix_identical_alone(dev):
         S = synth.make_library(w)
         X, s = synth.make_cube(w)
         libs[i] = linmin.Library(S)
-        pools[i] = (torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev), X, s)
+        pools[i] = (torch.from_numpy(X).to(dev), torch.from_numpy(s).to(dev), X, s,
+                    torch.from_numpy(X).pin_memory(), torch.from_numpy(s).pin_memory())
         hostS[i] = S
     reqs = []
     for rid in range(24):
         k = int(rng.integers(0, len(shapes)))
         P = int(round(np.exp(rng.uniform(np.log(50), np.log(3000)))))
         off = int(rng.integers(0, 4000 - P + 1))
-        Xd, sd, _, _ = pools[k]
+        Xd, sd, _, _, Xh, sh = pools[k]
+        if rid % 3 == 2:
+            Xd, sd = Xh, sh
         reqs.append(serve.Request(rid, k, Xd[off:off + P], sd[off:off + P], arrival=float(rng.uniform(0, 0.05))))
         reqs[-1].off = off
-    fps = sorted(serve.footprint(libs[r.lib], r.cube.shape[0], "fp64", "full") for r in reqs)
+    fps = sorted(serve.footprint(libs[r.lib], r.cube.shape[0], "fp64", "full", r.cube.device.type == "cpu")
+                 for r in reqs)
     budget = 3 * fps[len(fps) // 2]
     srv = serve.Server(libs, streams=4, slots=6, hbm_budget=budget, cov="full")
     done = srv.run(reqs)
@@ -624,12 +629,13 @@ def test_serving_mix_identical_alone(dev):
     assert srv.stats["max_running"] >= 2
     assert srv.stats["max_bytes"] <= max(budget, fps[-1])
     for r in done:
-        alone = libs[r.lib].unmix(r.cube, r.sigma, precision="fp64", cov="full")
+        alone = libs[r.lib].unmix(r.cube.to(dev), r.sigma.to(dev), precision="fp64", cov="full")
         torch.cuda.synchronize()
         for key in ("a", "cov", "status", "iters", "objective"):
             assert torch.equal(r.out[key].nan_to_num(3.5), alone[key].nan_to_num(3.5)), (r.rid, key)
+    assert sum(r.cube.device.type == "cpu" for r in done) == 8
     for r in done[:6]:
-        _, _, X, s = pools[r.lib]
+        _, _, X, s, _, _ = pools[r.lib]
         k = min(8, r.cube.shape[0])
         ro = oracle.unmix(hostS[r.lib], X[r.off:r.off + k], s[r.off:r.off + k], cov=False)
         assert np.abs(r.out["a"][:k].cpu().numpy() - ro["a"]).max() <= 1e-6

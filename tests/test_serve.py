@@ -43,3 +43,16 @@ def test_pick_passes_a_blocked_head_for_a_bounded_time():
     big.footprint = 500
     assert serve.pick(w, 0, 100, 0, 4, now=0.2, max_pass_s=0.5) == 0
     assert serve.pick([], 0, 100, 0, 4, now=0.0, max_pass_s=0.5) is None
+
+
+def test_footprint_counts_the_device_copy_of_a_host_cube():
+    class Lib:
+        N, L = 10, 100
+
+        def workspace_bytes(self, P, precision, cov):
+            return 1000
+
+    dev = serve.footprint(Lib(), 50, "fp64", "full")
+    host = serve.footprint(Lib(), 50, "fp64", "full", host_input=True)
+    assert dev == 50 * (8 * 10 + 8 * 100 + 1 + 4 + 8) + 1000
+    assert host - dev == 50 * (4 * 100 + 4)
