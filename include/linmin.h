@@ -104,7 +104,7 @@ typedef struct {
     double lambda0;     /* starting multipliers (0.1) */
     double tau;         /* KKT sign tolerance of the finishing step (1e-11) */
     double deg_tol;     /* strict-complementarity threshold (1e-9) */
-    double mu_switch;   /* MIXED: FP32 -> FP64 hand-over point (1e-8); the
+    double mu_switch;   /* MIXED: FP32 -> FP64 hand-over point (1e-10); the
                            FP32 stage also hands over after 60 steps or a
                            step below 1e-3 of the way to the boundary */
     uint8_t *status;    /* device, P entries or NULL: LINMIN_PX_* bits */

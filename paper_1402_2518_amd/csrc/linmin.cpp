@@ -268,7 +268,7 @@ void linmin_default_opts(linmin_opts* o) {
   o->lambda0 = 0.1;
   o->tau = 1e-11;
   o->deg_tol = 1e-9;
-  o->mu_switch = 1e-8;
+  o->mu_switch = 1e-10;
   o->status = nullptr;
   o->iters = nullptr;
   o->objective = nullptr;

@@ -78,7 +78,7 @@ def test_strerror_and_defaults_without_gpu():
     assert lib.linmin_strerror(-4).decode().startswith("matrix not")
     o = linmin.default_opts()
     assert o.maxit == 200 and o.tol_mu == 1e-13 and o.precision == linmin.FP64
-    assert o.mu_switch == 1e-8
+    assert o.mu_switch == 1e-10
     assert o.constraint == linmin.STO
     h = ctypes.c_void_p()
     # argument errors are reported before any device work

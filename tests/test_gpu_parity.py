@@ -72,16 +72,21 @@ def _compare(g, r, S, X, C=None, constraint="sto", a_tol=1e-6, cov_tol=1e-6, f_t
     minimiser), and the uncertified side's objective exceeds the certified
     one by no more than the bound on an interior iterate that met the
     stopping tests (complementarity gap plus dual residual times the
-    distance to the minimiser)."""
+    distance to the minimiser); the coefficient tolerance applies to the
+    pixels whose statuses agree."""
     assert np.isfinite(g["a"]).all()
-    da = np.abs(g["a"] - r["a"]).max()
-    assert da <= a_tol, f"max |a_gpu - a_oracle| = {da}"
     ok = (g["status"] == 0) & (r["status"] == 0)
     assert ok.mean() > 0.95, np.bincount(g["status"])
     mask = ~np.uint8(oracle.DEGENERATE)
     gs, rs = g["status"] & mask, r["status"] & mask
     same = gs == rs
     one_certified = ((gs == 0) & (rs == oracle.INEXACT)) | ((gs == oracle.INEXACT) & (rs == 0))
+    # coefficients where the statuses agree; a pixel certified on one side
+    # only is judged by the proof below (its uncertified side is an interior
+    # iterate, which may lie farther from the minimiser than the tolerance
+    # along a nearly flat direction of the objective)
+    da = np.abs(g["a"] - r["a"])[same].max() if same.any() else 0.0
+    assert da <= a_tol, f"max |a_gpu - a_oracle| = {da}"
     diff = np.flatnonzero(~same)
     info = [(int(i), int(g["status"][i]), int(r["status"][i]), int(g["iters"][i]), int(r["iters"][i]),
              float(np.abs(g["a"][i] - r["a"][i]).max())) for i in diff[:8]]
@@ -213,12 +218,13 @@ def test_mixed_retry_reproduces_fp64(dev):
     did not certify after the hand-over, so a pixel that the mixed form
     reports uncertified carries exactly the FP64 path's outputs (same
     kernel, same inputs), bit for bit; on this sum-lower-than-one mixture at
-    N = 64 the hand-over leaves such pixels.  Every other pixel meets the
-    oracle within the mixed tolerances."""
+    N = 64, with the hand-over at 1e-8, pixels that the FP64 path cannot
+    certify are left uncertified by the mixed form's FP64 steps as well.
+    Every other pixel meets the oracle within the mixed tolerances."""
     _say("[gpu] mixed-form retry pass, N = 64 sum-lower-than-one")
     S, X, s = _straddling(64, 128, 403, seed=164)
     g64 = _gpu(S, X, s, dev, precision="fp64", constraint="slo")
-    gmx = _gpu(S, X, s, dev, precision="mixed", constraint="slo")
+    gmx = _gpu(S, X, s, dev, precision="mixed", constraint="slo", mu_switch=1e-8)
     unc = (gmx["status"] & (oracle.INEXACT | oracle.MAXIT | oracle.NOT_PD)) != 0
     assert unc.any()
     for key in ("a", "status", "iters", "objective"):
