@@ -115,6 +115,9 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
   int mmax = small ? q - 1 : -1;
   mmax = max(mmax, __shfl_xor(mmax, 16));
   mmax = max(mmax, __shfl_xor(mmax, 32));
+  // the same on every lane: keep it scalar, so the guards below are scalar
+  // branches rather than per-lane masks
+  mmax = __builtin_amdgcn_readfirstlane(mmax);
   bool singular = false;
   static_for<0, Q>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
