@@ -34,21 +34,29 @@ __device__ __forceinline__ void gemm_proj_body(const float* __restrict__ Y, int6
   double sq = 0.0;
   for (int c0 = 0; c0 < L; c0 += 16) {
     const int ch0 = c0 + 4 * g;
+    // Every load of the chunk is issued unconditionally from a clamped
+    // channel and the values past L are zeroed afterwards: a guarded load
+    // becomes a branch that waits for its own result, which serialises the
+    // chunk's memory latency.  y = 0 makes the clamped W row irrelevant.
+    float yf[4];
+    double w[4][NT];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t ch = min(ch0 + s, L - 1);
+      yf[s] = yrow[ch];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) w[s][t] = W[ch * ldw + t * 16 + row];
+    }
     double y[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int ch = ch0 + s;
-      y[s] = (prow && ch < L) ? (double)yrow[ch] : 0.0;
+      y[s] = (prow && ch0 + s < L) ? (double)yf[s] : 0.0;
       sq = __builtin_fma(y[s], y[s], sq);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int ch = ch0 + s;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const double w = (ch < L) ? W[(int64_t)ch * ldw + t * 16 + row] : 0.0;
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s], w, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s], w[s][t], acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -101,12 +109,21 @@ __device__ __forceinline__ void quadform_body(const float* __restrict__ Y, int64
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     for (int c0 = 0; c0 < L; c0 += 16) {
       const int ch0 = c0 + 4 * g;
+      // unconditional loads from clamped indices, zeroed afterwards (as in
+      // the projections above)
+      const int col = min(t0 + row, L - 1);
+      float yf[4];
+      double w[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int ch = ch0 + s;
-        const double y = (prow && ch < L) ? (double)yrow[ch] : 0.0;
-        const double w = (ch < L && t0 + row < L) ? Ci[(int64_t)ch * ldc + t0 + row] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(y, w, acc, 0, 0, 0);
+        const int64_t ch = min(ch0 + s, L - 1);
+        yf[s] = yrow[ch];
+        w[s] = Ci[ch * ldc + col];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double y = (prow && ch0 + s < L) ? (double)yf[s] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(y, (t0 + row < L) ? w[s] : 0.0, acc, 0, 0, 0);
       }
     }
     const int col = t0 + row;
