@@ -45,6 +45,23 @@ __device__ __forceinline__ double rowbcast(double v) {
   return dpp<0x150 + K>(v);
 }
 
+// r += be * (r on lane K of this lane's 16-lane row): one 64-bit FMA with a
+// row broadcast on its first source.  The s_nop gives the two wait states a
+// DPP read needs after a vector write of its source register.
+template <int K>
+__device__ __forceinline__ void fmac_bcast(double& r, double be) {
+  asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+               : "+v"(r)
+               : "v"(be), "i"(K));
+}
+// r += be * (src on lane K of this lane's 16-lane row)
+template <int K>
+__device__ __forceinline__ void fmac_bcast_from(double& r, double src, double be) {
+  asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(r)
+               : "v"(src), "v"(be), "i"(K));
+}
+
 }  // namespace
 
 // Covariance of pixel p on the calling 16-lane row (live = the row has a
@@ -119,6 +136,13 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
   // branches rather than per-lane masks
   mmax = __builtin_amdgcn_readfirstlane(mmax);
   bool singular = false;
+  // Each row keeps the scale of its own pivot step deferred: at pivot k the
+  // pivot row is left as it is (its pivot entry becomes -1) and rs = 1/akk
+  // is kept for it; the sweep is linear in each row, so the later steps
+  // apply to the unscaled row unchanged, and every row is scaled once at the
+  // end.  Each entry update is then one FMA that reads the pivot row's entry
+  // from lane kt of the DPP row (fmac_bcast).
+  double rs0 = 1.0, rs1 = 1.0;  // deferred scales of rows t and t + 16
   static_for<0, Q>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
     constexpr int kh = k / 16, kt = k % 16;
@@ -126,35 +150,37 @@ __device__ __forceinline__ void cov_group(int n, int64_t p, bool live, const dou
       const double akk = rowbcast<kt>(R[kh][k]);
       if (!(akk != 0.0) || akk != akk) singular = true;
       const double r = 1.0 / akk;
-      // row update R_j <- al R_j + be K_kj: the pivot row is scaled by 1/akk
-      // (al = r, be = 0), every other row loses f = R_k / akk times the pivot
-      // row (al = 1, be = -f); the pivot column becomes f (-r on the pivot)
-      double al[H], be[H];
-      static_for<0, H>([&](auto hh) {
-        constexpr int h = decltype(hh)::value;
-        const bool prow = (t + 16 * h == k);
-        al[h] = prow ? r : 1.0;
-        be[h] = prow ? 0.0 : -(R[h][k] * r);
-      });
+      // rows other than the pivot lose f = R_k / akk times the pivot row
+      // (be = -f); the pivot column becomes f (-1 on the deferred pivot row)
+      const bool p0 = t == k, p1 = H == 2 && t + 16 == k;
+      const double f0 = R[0][k] * r;
+      const double f1 = H == 2 ? R[H - 1][k] * r : 0.0;
+      const double be0 = p0 ? 0.0 : -f0, be1 = p1 ? 0.0 : -f1;
+      rs0 = p0 ? r : rs0;
+      rs1 = p1 ? r : rs1;
       static_for<0, Q>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         if (j <= mmax) {
-          if constexpr (j == k) {
-            static_for<0, H>([&](auto hh) {
-              constexpr int h = decltype(hh)::value;
-              R[h][j] = (t + 16 * h == k) ? -r : -be[h];
-            });
-          } else {
-            // K_kj before the step, read before any row of this column changes
-            const double b = rowbcast<kt>(R[kh][j]);
-            static_for<0, H>([&](auto hh) {
-              constexpr int h = decltype(hh)::value;
-              R[h][j] = fmaT(be[h], b, al[h] * R[h][j]);
-            });
+          if constexpr (j != k) {
+            // the pivot row's entry is not changed by the step (be = 0 on
+            // its lane), so the order of the rows does not matter
+            if constexpr (kh == 0) fmac_bcast<kt>(R[0][j], be0);
+            else fmac_bcast_from<kt>(R[0][j], R[kh][j], be0);
+            if constexpr (H == 2) {
+              if constexpr (kh == 1) fmac_bcast<kt>(R[H - 1][j], be1);
+              else fmac_bcast_from<kt>(R[H - 1][j], R[0][j], be1);
+            }
           }
         }
       });
+      R[0][k] = p0 ? -1.0 : f0;
+      if constexpr (H == 2) R[H - 1][k] = p1 ? -1.0 : f1;
     }
+  });
+  static_for<0, Q>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    R[0][c] *= rs0;
+    if constexpr (H == 2) R[H - 1][c] *= rs1;
   });
   if (!small) return;
 
