@@ -56,6 +56,21 @@ def _compile(src, obj, extra=()):
     return obj
 
 
+# Instruction scheduling per four-pixel FP64 tile shape.  The T = 16 shape
+# (N = 49..64) runs at one wave per SIMD with spilled registers, so nothing
+# hides its latencies but the order of its own instructions; LLVM's
+# latency-first ("max-ilp") strategy spills less there (243 vs 312 VGPRs)
+# and runs 4.5 % faster on the precision cube (69.3 vs 72.7 ms).  Every other
+# interior-point shape measured slower with it (T = 9 and 12, the FP32 and
+# row-cyclic kernels) and keeps the default.
+TILE_FLAGS = {"16": ("-mllvm", "-amdgpu-sched-strategy=max-ilp")}
+
+
+def tile_flags(t: str) -> tuple:
+    """Compiler flags of the four-pixel FP64 tile shape T = t."""
+    return (f"-DLM_TILE_T={t}",) + TILE_FLAGS.get(t, ())
+
+
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = []
@@ -65,8 +80,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         units.append((os.path.join(CSRC, "ipm.hip"), os.path.join(BUILD, f"ipm_{t}_{nc}_{g}.o"),
                       (f"-DLM_T={t}", f"-DLM_NC={nc}", f"-DLM_G={g}")))
     for t in tiles():
-        units.append((os.path.join(CSRC, "ipm_tile.hip"), os.path.join(BUILD, f"ipm_tile_{t}.o"),
-                      (f"-DLM_TILE_T={t}",)))
+        units.append((os.path.join(CSRC, "ipm_tile.hip"), os.path.join(BUILD, f"ipm_tile_{t}.o"), tile_flags(t)))
     for t in tile32s():
         units.append((os.path.join(CSRC, "ipm_tile32.hip"), os.path.join(BUILD, f"ipm_tile32_{t}.o"),
                       (f"-DLM_TILE32_T={t}",)))
