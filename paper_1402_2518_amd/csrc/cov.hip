@@ -46,8 +46,11 @@ __device__ __forceinline__ double rowbcast(double v) {
 }
 
 // r += be * (r on lane K of this lane's 16-lane row): one 64-bit FMA with a
-// row broadcast on its first source.  The s_nop gives the two wait states a
-// DPP read needs after a vector write of its source register.
+// row broadcast on its first source.  The compiler does not see the DPP
+// inside the asm, so the asm brings the two wait states a DPP read needs
+// after a vector write of its source register.  A scalar write of EXEC needs
+// five; the sweeps change EXEC only outside their pivot loops (the guards
+// there are scalar branches), which a test checks on the built code.
 template <int K>
 __device__ __forceinline__ void fmac_bcast(double& r, double be) {
   asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
